@@ -1,0 +1,320 @@
+"""FP64 reference of the BioEM posterior (test infrastructure, see package doc).
+
+Conventions (each one a reading of the paper, listed with its reason in the
+design notes of the repository):
+
+* Images are arrays ``I[k][j]`` with row index k along y and column index j
+  along x; pixel (j, k) has centre ``x_j = (j - Nx/2) * pixel``,
+  ``y_k = (k - Ny/2) * pixel``.
+* Fourier transforms follow numpy: forward ``exp(-2 pi i (l k/Ny + m j/Nx))``
+  without normalisation, inverse with ``1/Npix``; half spectra are laid out
+  ``[Ny][Nx/2+1]`` and the signed row frequency is ``l`` for ``l <= Ny/2`` and
+  ``l - Ny`` above.  The paper's Eqs. (1)-(2) print 1-based sums without the
+  ``1/N`` inside the exponent; this is the standard 0-based DFT they denote.
+* The displacement d enters as ``I_cal(r) = N I1(r + d) - mu`` (Section 2,
+  calculated image), so the correlation at d is ``sum_r I_o(r) I1(r + d)``
+  with indices taken modulo the box: the Fourier variant of Section 3
+  (Center displacement) wraps around the borders, and the oracle computes the
+  same circular function directly.
+* Shifts cover the square window ``|dx|, |dy| <= S`` in 1-pixel steps.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass
+from typing import Optional, Sequence
+
+import numpy as np
+from scipy.special import erf
+
+
+# ---------------------------------------------------------------------------
+# Model rotation and projection (Section 2, Eq. ideal; Section 3, Model rotation)
+# ---------------------------------------------------------------------------
+
+def quat_to_matrix(q: Sequence[float]) -> np.ndarray:
+    """Rotation matrix of the unit quaternion q = (w, x, y, z) (Hamilton, active).
+
+    The paper parametrises orientations by quaternions (Section 3, Model
+    rotation); r' = R(q) r rotates the model about its origin.  q and -q give
+    the same matrix.
+    """
+    w, x, y, z = np.asarray(q, dtype=np.float64) / np.linalg.norm(q)
+    return np.array([
+        [1 - 2 * (y * y + z * z), 2 * (x * y - w * z), 2 * (x * z + w * y)],
+        [2 * (x * y + w * z), 1 - 2 * (x * x + z * z), 2 * (y * z - w * x)],
+        [2 * (x * z - w * y), 2 * (y * z + w * x), 1 - 2 * (x * x + y * y)],
+    ])
+
+
+def _pixel_integrals(centres: np.ndarray, pos: np.ndarray, sigma: np.ndarray,
+                     pixel: float) -> np.ndarray:
+    """[n_spheres][n_pixels] integral of a unit 1-D Gaussian over each pixel."""
+    s = np.sqrt(2.0) * sigma[:, None]
+    u = centres[None, :] - pos[:, None]
+    return 0.5 * (erf((u + 0.5 * pixel) / s) - erf((u - 0.5 * pixel) / s))
+
+
+def project_model(spheres: np.ndarray, q: Sequence[float], nx: int, ny: int,
+                  pixel: float) -> np.ndarray:
+    """Ideal projection I0[k][j] of a Gaussian-sphere model, Eq. (ideal).
+
+    The density is a sum of normalised 3-D Gaussians of weight w_a, centre
+    r_a and width sigma_a.  Rotating by q and integrating along z over the
+    whole line and over the pixel box in x and y leaves, for each sphere, the
+    product of two 1-D pixel integrals, so
+    I0[k][j] = sum_a w_a Ey[a][k] Ex[a][j].
+    """
+    sp = np.asarray(spheres, dtype=np.float64)
+    r = sp[:, :3] @ quat_to_matrix(q).T
+    xc = (np.arange(nx) - nx // 2) * pixel
+    yc = (np.arange(ny) - ny // 2) * pixel
+    ex = _pixel_integrals(xc, r[:, 0], sp[:, 3], pixel)
+    ey = _pixel_integrals(yc, r[:, 1], sp[:, 3], pixel)
+    return (ey * sp[:, 4][:, None]).T @ ex
+
+
+# ---------------------------------------------------------------------------
+# CTF and envelope, Fourier filtering (Section 2, Eqs. 3-4)
+# ---------------------------------------------------------------------------
+
+def signed_freq(n: int) -> np.ndarray:
+    """Signed integer frequency of each index of an n-point DFT axis."""
+    k = np.arange(n)
+    return np.where(k <= n // 2, k, k - n)
+
+
+def ctf_envelope_table(a: float, amp: float, b: float, nx: int, ny: int,
+                       pixel: float) -> np.ndarray:
+    """CTF(s|a,A) Env(s|b) on the half spectrum [Ny][Nx/2+1] (Section 2).
+
+    CTF(s) = -A cos(a s^2/2) - sqrt(1 - A^2) sin(a s^2/2) and
+    Env(s) = exp(-b s^2/2), where s = |s| and s = 2 pi (m/(Nx dx), l/(Ny dy))
+    for signed integer frequencies (m, l).
+    """
+    m = np.arange(nx // 2 + 1)
+    l = signed_freq(ny)
+    s2 = (2.0 * np.pi) ** 2 * ((m[None, :] / (nx * pixel)) ** 2
+                               + (l[:, None] / (ny * pixel)) ** 2)
+    ph = 0.5 * a * s2
+    ctf = -amp * np.cos(ph) - math.sqrt(1.0 - amp * amp) * np.sin(ph)
+    return ctf * np.exp(-0.5 * b * s2)
+
+
+def filtered_projection(i0: np.ndarray, table: np.ndarray) -> np.ndarray:
+    """I1 = F^-1[F(I0) CTF Env], Eq. (4); real because the filter is radial."""
+    ny, nx = i0.shape
+    return np.fft.irfft2(np.fft.rfft2(i0) * table, s=(ny, nx))
+
+
+# ---------------------------------------------------------------------------
+# Precomputed sums and the cross-correlation (Section 3; Center displacement)
+# ---------------------------------------------------------------------------
+
+def image_moments(img: np.ndarray):
+    """(C_o, C_oo, A) of an observed image, in FP64 from pixels.
+
+    C_o = sum I, C_oo = sum I^2 (the per-image constants the paper
+    precomputes) and A = sum (I - C_o/n)^2 = C_oo - C_o^2/n, taken in two
+    passes so that no cancellation occurs.
+    """
+    x = np.asarray(img, dtype=np.float64)
+    c_o = math.fsum(x.ravel())
+    c_oo = math.fsum((x * x).ravel())
+    mean = c_o / x.size
+    d = x - mean
+    return c_o, c_oo, math.fsum((d * d).ravel())
+
+
+def projection_norm(i1: np.ndarray) -> float:
+    """B = sum (I1 - mean)^2 of a calculated image (shift-invariant, circular)."""
+    x = np.asarray(i1, dtype=np.float64)
+    d = x - math.fsum(x.ravel()) / x.size
+    return math.fsum((d * d).ravel())
+
+
+def correlation_direct(img: np.ndarray, i1: np.ndarray, S: int) -> np.ndarray:
+    """X[dy+S][dx+S] = sum_r (I_o(r) - mean) I1((r + d) mod box), directly.
+
+    This is the real-space cross-correlation of Section 3 with the wrap of
+    the Fourier variant; centring the image removes the offset so X is the
+    covariance-type sum the marginal likelihood needs.  Batched over a
+    leading image axis when ``img`` is 3-D.
+    """
+    imgs = np.asarray(img, dtype=np.float64)
+    single = imgs.ndim == 2
+    if single:
+        imgs = imgs[None]
+    ni, ny, nx = imgs.shape
+    ic = (imgs - imgs.reshape(ni, -1).mean(axis=1)[:, None, None]).reshape(ni, -1)
+    p = np.asarray(i1, dtype=np.float64)
+    w = 2 * S + 1
+    out = np.empty((ni, w, w))
+    for dy in range(-S, S + 1):
+        stack = np.stack([np.roll(p, (-dy, -dx), axis=(0, 1)).ravel()
+                          for dx in range(-S, S + 1)], axis=1)
+        out[:, dy + S, :] = ic @ stack
+    return out[0] if single else out
+
+
+def correlation_fft(img: np.ndarray, i1: np.ndarray, S: int) -> np.ndarray:
+    """The same window via Eq. (fourier): F^-1[conj(F(I_o)) F(I1)] at d.
+
+    Faster reference for large boxes; equal to ``correlation_direct`` up to
+    FP64 rounding (pinned by a test).  Batched like ``correlation_direct``.
+    """
+    imgs = np.asarray(img, dtype=np.float64)
+    single = imgs.ndim == 2
+    if single:
+        imgs = imgs[None]
+    ni, ny, nx = imgs.shape
+    ic = imgs - imgs.reshape(ni, -1).mean(axis=1)[:, None, None]
+    full = np.fft.irfft2(np.conj(np.fft.rfft2(ic)) * np.fft.rfft2(np.asarray(i1, np.float64)),
+                         s=(ny, nx))
+    d = np.arange(-S, S + 1)
+    out = full[:, (d % ny)[:, None], (d % nx)[None, :]]
+    return out[0] if single else out
+
+
+# ---------------------------------------------------------------------------
+# Marginal likelihood (Section 2, Eq. likeli; Section 3, analytic integration)
+# ---------------------------------------------------------------------------
+
+_RHO2_MAX = 1.0 - 2.0 ** -52
+
+
+def log_likelihood(X, A: float, B: float, n: int):
+    """ln of Eq. (likeli) integrated over offset mu, scale N and noise lambda.
+
+    With I_cal = N I1' - mu, flat priors on mu and N over the real line and
+    the scale-invariant prior 1/lambda, the three integrals are Gaussian,
+    Gaussian and Gamma in turn:
+      int dmu   -> sqrt(2 pi lambda^2 / n)
+      int dN    -> sqrt(2 pi lambda^2 / B)
+      int dl/l  -> (1/2) Gamma(n/2 - 1) (Q/2)^(1 - n/2),  Q = A - X^2/B,
+    so L = (1/2) Gamma(n/2-1) (pi Q)^(1-n/2) / sqrt(n B).  Here A is the
+    centred sum of squares of the image, B that of the calculated image and X
+    their centred cross-correlation.  Writing Q = A (1 - X^2/(A B)) keeps the
+    large terms separate from the small correlation term.  1 - rho^2 is
+    clamped at 2^-52 (an exact noise-free fit would diverge).
+    """
+    X = np.asarray(X, dtype=np.float64)
+    rho2 = np.minimum(X * X / (A * B), _RHO2_MAX)
+    h = 0.5 * n
+    const = (math.lgamma(h - 1.0) - math.log(2.0) - 0.5 * math.log(n)
+             + (1.0 - h) * math.log(math.pi * A) - 0.5 * math.log(B))
+    return const + (1.0 - h) * np.log1p(-rho2)
+
+
+def logsumexp_exact(values) -> float:
+    """ln sum exp(v) as M + ln fsum(exp(v - M)) in FP64."""
+    v = np.asarray(values, dtype=np.float64).ravel()
+    m = float(np.max(v))
+    return m + math.log(math.fsum(np.exp(v - m)))
+
+
+# ---------------------------------------------------------------------------
+# Posterior over the grid (Eq. Pmom; Listing 1's loop nest)
+# ---------------------------------------------------------------------------
+
+@dataclass
+class OracleResult:
+    logp: np.ndarray          # [ni] log posterior per image (relative, see log_prior)
+    best_logl: np.ndarray     # [ni] maximal log-likelihood
+    best_q: np.ndarray        # [ni]
+    best_c: np.ndarray        # [ni]
+    best_dx: np.ndarray       # [ni]
+    best_dy: np.ndarray       # [ni]
+    logp_orient: np.ndarray   # [ni][nq] log posterior restricted to orientation q
+    log_prior: float          # -ln(Nq Nc Nd): uniform normalised grid prior
+
+
+def logpost_oracle(images: np.ndarray, spheres: np.ndarray, quats: np.ndarray,
+                   ctfs: np.ndarray, pixel: float, S: int, method: str = "direct",
+                   q_subset: Optional[Sequence[int]] = None) -> OracleResult:
+    """log P_{m,omega} for every image over the orientation x CTF x shift grid.
+
+    P is the integral of Eq. (Pmom) with mu, N and lambda integrated
+    analytically (``log_likelihood``) and the remaining parameters summed over
+    their grids with uniform normalised priors:
+      log P = ln sum_{q,c,d} exp(l(q,c,d)) - ln(Nq Nc Nd).
+    The loop nest follows Listing 1: rotation and projection outermost, then
+    the CTF filter, then all images at every displacement.  Also returns the
+    maximising grid point (ties go to the lowest (q, c, dy, dx)) and the
+    posterior restricted to each orientation (LSE over c and d).
+    ``q_subset`` evaluates only those orientations (the prior keeps Nq).
+    """
+    imgs = np.asarray(images, dtype=np.float64)
+    ni, ny, nx = imgs.shape
+    n = nx * ny
+    nq, nc = len(quats), len(ctfs)
+    nd = (2 * S + 1) ** 2
+    corr = {"direct": correlation_direct, "fft": correlation_fft}[method]
+    A = np.array([image_moments(im)[2] for im in imgs])
+    tables = [ctf_envelope_table(a, amp, b, nx, ny, pixel) for a, amp, b in ctfs]
+    qs = range(nq) if q_subset is None else q_subset
+    orient = np.full((ni, nq), -np.inf)
+    best = np.full(ni, -np.inf)
+    bq = np.zeros(ni, np.int64)
+    bc = np.zeros(ni, np.int64)
+    bdx = np.zeros(ni, np.int64)
+    bdy = np.zeros(ni, np.int64)
+    log_prior = -math.log(nq) - math.log(nc) - math.log(nd)
+    for q in qs:
+        i0 = project_model(spheres, quats[q], nx, ny, pixel)
+        per_c = np.empty((ni, nc, 2 * S + 1, 2 * S + 1))
+        for c in range(nc):
+            i1 = filtered_projection(i0, tables[c])
+            B = projection_norm(i1)
+            X = corr(imgs, i1, S)
+            for i in range(ni):
+                per_c[i, c] = log_likelihood(X[i], A[i], B, n)
+        for i in range(ni):
+            orient[i, q] = logsumexp_exact(per_c[i]) + log_prior
+            flat = per_c[i].ravel()
+            k = int(np.argmax(flat))      # first maximum = lowest (c, dy, dx)
+            if flat[k] > best[i]:         # strict: an earlier q keeps a tie
+                best[i] = flat[k]
+                c, rem = divmod(k, (2 * S + 1) ** 2)
+                dyi, dxi = divmod(rem, 2 * S + 1)
+                bq[i], bc[i], bdy[i], bdx[i] = q, c, dyi - S, dxi - S
+    sel = np.array(list(qs))
+    logp = np.array([logsumexp_exact(orient[i, sel]) for i in range(ni)])
+    return OracleResult(logp=logp, best_logl=best, best_q=bq, best_c=bc, best_dx=bdx,
+                        best_dy=bdy, logp_orient=orient, log_prior=log_prior)
+
+
+# ---------------------------------------------------------------------------
+# Synthetic map (Section 3, Extra features): a calculated image for given theta
+# ---------------------------------------------------------------------------
+
+def render_image(spheres: np.ndarray, q, ctf, shift, nx: int, ny: int, pixel: float,
+                 norm: float = 1.0, offset: float = 0.0, noise: Optional[np.ndarray] = None,
+                 snr: Optional[float] = None) -> np.ndarray:
+    """I_cal(r) = N I1(r + d) - mu, plus optional Gaussian noise at a given SNR.
+
+    SNR is var(clean)/sigma_n^2 over the whole box with i.i.d. pixel noise,
+    the noise model of Eq. (likeli).  Returns FP64; callers store FP32.
+    """
+    a, amp, b = ctf
+    i1 = filtered_projection(project_model(spheres, q, nx, ny, pixel),
+                             ctf_envelope_table(a, amp, b, nx, ny, pixel))
+    dx, dy = int(shift[0]), int(shift[1])
+    clean = np.roll(i1, (-dy, -dx), axis=(0, 1))
+    out = norm * clean - offset
+    if noise is not None:
+        sigma = math.sqrt(float(np.var(clean)) / snr)
+        out = out + sigma * np.asarray(noise, dtype=np.float64)
+    return out
+
+
+def render_images(cls, models, i0: int = 0, i1: Optional[int] = None) -> np.ndarray:
+    """FP32 images [i1-i0][ny][nx] of a workload size class, rendered in FP64."""
+    i1 = cls.n_images if i1 is None else i1
+    noise = cls.noise(i0, i1)
+    out = np.empty((i1 - i0, cls.ny, cls.nx), np.float32)
+    for j, i in enumerate(range(i0, i1)):
+        out[j] = render_image(models[cls.img_model[i]], cls.img_quat[i], cls.img_ctf[i],
+                              cls.img_shift[i], cls.nx, cls.ny, cls.pixel_A,
+                              cls.img_norm[i, 0], cls.img_norm[i, 1], noise[j], cls.snr)
+    return out
