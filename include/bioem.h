@@ -1,0 +1,181 @@
+/*
+ * bioem.h - C ABI of the MI355X (gfx950) BioEM posterior engine.
+ *
+ * Computes, for every particle image omega and model m, the posterior of the
+ * model given the image (Eq. Pmom of Cossio, Rohr et al., "BioEM:
+ * GPU-accelerated computing of Bayesian inference of electron microscopy
+ * images"): the likelihood of Eq. (likeli) integrated analytically over
+ * normalisation N, offset mu and noise lambda, and numerically over a grid of
+ * orientations (quaternions), CTF/envelope parameter sets (a, A, b) and
+ * in-plane displacements d with |dx|, |dy| <= S.
+ *
+ * Conventions shared by every call
+ *   - Images are row-major [ny][nx] float32; pixel (j, k) is centred at
+ *     ((j - nx/2) * pixel, (k - ny/2) * pixel) in Angstrom.
+ *   - Quaternions are (w, x, y, z), active rotation about the model origin.
+ *   - Fourier transforms: forward exp(-2 pi i (l k/ny + m j/nx)), inverse with
+ *     1/(nx ny) (the paper's Eqs. 1-2 read as the standard 0-based DFT).
+ *   - The displacement enters as I_cal(r) = N I1(r + d) - mu (Section 2), with
+ *     indices taken modulo the box, which is the Fourier variant of Section 3
+ *     (Center displacement).
+ *   - Priors: flat in mu and N, 1/lambda in lambda, uniform normalised over the
+ *     orientation, CTF and shift grids, so
+ *       log P = ln sum_{q,c,d} exp(l(q,c,d)) - ln(Nq Nc Nd)
+ *     with l(q,c,d) = lgamma(n/2-1) - ln 2 - ln(n)/2 + (1-n/2) ln(pi A)
+ *                     - ln(B_qc)/2 + (1-n/2) log1p(-X(d)^2/(A B_qc)),
+ *     A = sum (I - mean)^2 of the image, B_qc the same of the calculated
+ *     image, X(d) their cross-correlation at shift d.  Values are relative:
+ *     the paper's posterior is defined up to a constant (Section 5).
+ *
+ * Memory and streams
+ *   - Every array argument is borrowed for the duration of the call; it is
+ *     host memory or device memory (a pointer valid on the context's device)
+ *     as the accompanying bioem_mem value says.
+ *   - The opaque handles bioem_proj / bioem_imgs own device arrays until
+ *     bioem_free_proj / bioem_free_imgs.
+ *   - All device work is enqueued on the context's stream.  A call that
+ *     writes host memory synchronises the stream before returning; a call
+ *     that writes device memory returns after enqueueing.
+ *
+ * Errors
+ *   - Every entry point returns a bioem_status; no C++ exception crosses the
+ *     ABI.  Arguments are validated before any work is enqueued.  On failure
+ *     bioem_last_error(ctx) describes the cause (valid until the next call on
+ *     the same context).  Per-image degeneracy (an image with zero variance,
+ *     or no calculated image with non-zero variance) is not an error: that
+ *     image gets status 1 and log P = NaN.
+ *   - One context per host thread; calls on one context are not thread-safe.
+ */
+#ifndef BIOEM_H
+#define BIOEM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct bioem_ctx bioem_ctx;
+typedef struct bioem_proj bioem_proj;
+typedef struct bioem_imgs bioem_imgs;
+
+typedef enum {
+  BIOEM_OK = 0,
+  BIOEM_EINVAL = -1,        /* invalid argument (sizes, ranges, non-finite values) */
+  BIOEM_ENOMEM = -2,        /* device allocation failed */
+  BIOEM_EDEVICE = -3,       /* HIP runtime error or kernel fault */
+  BIOEM_EUNSUPPORTED = -4   /* valid but outside what this build supports */
+} bioem_status;
+
+typedef enum { BIOEM_MEM_HOST = 0, BIOEM_MEM_DEVICE = 1 } bioem_mem;
+
+/* How the inverse transforms of the cross-correlation are computed.
+ *   F32:        FP32 direct pruned transform on the vector ALUs.
+ *   SPLIT_F16:  DFT-as-GEMM on the matrix cores; each FP32 operand is split
+ *               into fp16 hi + lo parts, three products, FP32 accumulation
+ *               (about 22 significant bits).
+ *   SPLIT_BF16: the same with bfloat16 hi + lo parts (about 16 bits).
+ * In every mode the likelihood constants, log1p and the log-sum-exp are FP64
+ * (the per-image constants reach ~1e5 nat at 224^2, Section 3 Numerical
+ * precision notwithstanding). */
+typedef enum {
+  BIOEM_PREC_F32 = 0,
+  BIOEM_PREC_SPLIT_BF16 = 1,
+  BIOEM_PREC_SPLIT_F16 = 2
+} bioem_prec;
+
+/* Maximising grid parameters of one image (Section 3, Extra features). */
+typedef struct {
+  double logl;     /* maximal log-likelihood l(q,c,d) */
+  int32_t q;       /* orientation index into the projection set */
+  int32_t c;       /* CTF set index */
+  int32_t dx, dy;  /* displacement in pixels, |dx|,|dy| <= S */
+  int32_t status;  /* 0 ok, 1 degenerate image (log P = NaN) */
+} bioem_best;
+
+typedef struct {
+  int32_t prec;            /* bioem_prec; 0 = F32 */
+  int32_t out_mem;         /* bioem_mem of logp, best and logp_orient */
+  /* Optional per-image candidate orientations (a proposal): cand_q is
+   * [ni][k] int32 indices into the projection set; only those orientations
+   * are evaluated, and log P keeps the full-grid prior -ln Nq, so it is a
+   * lower bound of the exhaustive value.  NULL evaluates the full grid. */
+  const int32_t* cand_q;
+  int32_t k;
+  int32_t cand_mem;        /* bioem_mem of cand_q */
+  /* Optional [ni][nq] output: log posterior restricted to each orientation
+   * (LSE over CTF sets and shifts, same prior), Section 3 Extra features.
+   * Entries not evaluated under a proposal are -inf. */
+  double* logp_orient;
+  int32_t reserved[4];     /* must be zero */
+} bioem_opts;
+
+/* Create a context on HIP device `device`.  `hip_stream` is a hipStream_t to
+ * enqueue on, or NULL for a stream the context creates and owns. */
+bioem_status bioem_create(int device, void* hip_stream, bioem_ctx** out);
+void bioem_destroy(bioem_ctx* ctx);
+const char* bioem_last_error(const bioem_ctx* ctx);
+/* Version string of the library build. */
+const char* bioem_version(void);
+
+/* Fourier-space projections of a Gaussian-sphere model (Section 2, Eq. ideal;
+ * Section 3, Model rotation).
+ *   spheres [ns][5] float64: centre x, y, z (A), width sigma (A), weight
+ *           (integral of the normalised 3-D Gaussian);
+ *   quats   [nq][4] float64 unit quaternions (w, x, y, z);
+ *   nx, ny  even box size in pixels (4 <= n <= 1024); pixel_A > 0.
+ * Each projection is I0[k][j] = sum_a w_a Ey_a[k] Ex_a[j] with pixel-box
+ * integrals of the rotated Gaussians (FP64), then its half-spectrum DFT,
+ * stored on the device.  *out must be released with bioem_free_proj. */
+bioem_status bioem_project(bioem_ctx* ctx, const double* spheres, int32_t ns,
+                           const double* quats, int32_t nq, int32_t nx, int32_t ny,
+                           double pixel_A, bioem_mem in_mem, bioem_proj** out);
+
+/* Observed images (Section 3: the spectra and per-image sums C_o, C_oo are
+ * precalculated).  imgs is [ni][ny][nx] float32.  Computes, in FP64 from the
+ * pixels, C_o = sum I, C_oo = sum I^2 and A = sum (I - C_o/n)^2, and the
+ * half-spectrum DFT of each image.  *out must be released with
+ * bioem_free_imgs. */
+bioem_status bioem_prepare_images(bioem_ctx* ctx, const float* imgs, int32_t ni, int32_t nx,
+                                  int32_t ny, bioem_mem in_mem, bioem_imgs** out);
+
+/* Per-image log posterior over orientations x CTF sets x shifts (Eq. Pmom,
+ * Listing 1).  ctf is [nc][3] float64 (a in A^2, A in [0,1], b in A^2) of
+ * CTF(s|a,A) Env(s|b) (Section 2); ctf is host or device per `ctf_mem`.
+ * max_shift = S with 0 <= S < min(nx, ny)/2.  Outputs: logp [ni] float64 and
+ * best [ni] (either may be NULL), and optional opts->logp_orient.  opts may
+ * be NULL (F32, host outputs, full grid). */
+bioem_status bioem_logpost(bioem_ctx* ctx, const bioem_proj* proj, const bioem_imgs* imgs,
+                           const double* ctf, int32_t nc, bioem_mem ctf_mem, int32_t max_shift,
+                           const bioem_opts* opts, double* logp, bioem_best* best);
+
+/* Synthetic maps (Section 3, Extra features): one calculated image per
+ * projection, I_cal(r) = N I1(r + d) - mu + sigma eps with
+ * I1 = F^-1[F(I0) CTF Env] and sigma^2 = var(I1)/snr.
+ *   proj holds ni projections (one per image); ctf [ni][3]; shifts [ni][2]
+ *   int32 (dx, dy); norm_offset [ni][2] (N, mu) or NULL for (1, 0); noise
+ *   [ni][ny][nx] float32 standard-normal draws or NULL for none (snr is then
+ *   ignored).  Inputs are host or device per in_mem; out [ni][ny][nx] float32
+ *   per out_mem. */
+bioem_status bioem_render(bioem_ctx* ctx, const bioem_proj* proj, const double* ctf,
+                          const int32_t* shifts, const double* norm_offset, const float* noise,
+                          double snr, bioem_mem in_mem, float* out, bioem_mem out_mem);
+
+void bioem_free_proj(bioem_proj* p);
+void bioem_free_imgs(bioem_imgs* p);
+
+/* Sizes of a handle: *n items of nx x ny pixels. */
+bioem_status bioem_proj_info(const bioem_proj* p, int32_t* n, int32_t* nx, int32_t* ny);
+bioem_status bioem_imgs_info(const bioem_imgs* p, int32_t* n, int32_t* nx, int32_t* ny);
+
+/* Map physical CTF parameters to the paper's (a, A, b): with s = 2 pi k and
+ * electron wavelength lambda(voltage), a = lambda defocus / (2 pi) and
+ * b = B / (8 pi^2), A = amplitude contrast.  Defocus > 0 is underfocus. */
+bioem_status bioem_ctf_from_physical(double defocus_A, double amp_contrast, double bfactor_A2,
+                                     double voltage_kV, double out_abA[3]);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* BIOEM_H */

@@ -1,0 +1,101 @@
+// Internal declarations shared by the BioEM HIP sources (not part of the ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+
+#include "../../include/bioem.h"
+
+struct bioem_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  std::string err;
+};
+
+// Half spectra are stored column-major per item: spec[item][m][l] with
+// m in [0, nx/2] (x frequency) and l in [0, ny) (y frequency), scaled by
+// 2^-expo[item] so that every |value| <= 1 (the split-precision kernels need
+// a bounded range; the scale is undone in FP64 in the likelihood epilogue).
+struct bioem_proj {
+  int32_t n = 0, nx = 0, ny = 0;
+  double pixel = 0.0;         // A per pixel (sets the CTF frequency scale)
+  float2* spec = nullptr;     // [n][nx/2+1][ny]
+  int32_t* expo = nullptr;    // [n]
+  int device = 0;
+};
+
+struct bioem_imgs {
+  int32_t n = 0, nx = 0, ny = 0;
+  float2* spec = nullptr;     // [n][nx/2+1][ny]
+  int32_t* expo = nullptr;    // [n]
+  double* stats = nullptr;    // [n][3]: C_o, C_oo, A
+  int device = 0;
+};
+
+// Per (image, evaluated orientation) partial result of the main kernels.
+struct bioem_rec {
+  double lse;     // ln sum over CTF sets and shifts of exp(l)
+  double bestl;   // max l over CTF sets and shifts
+  int32_t q;      // orientation index
+  int32_t c;      // CTF index of the maximum
+  int32_t d;      // (dy+S)*(2S+1) + (dx+S) of the maximum
+  int32_t pad;
+};
+
+namespace bioem {
+
+constexpr int kMaxBox = 512;
+
+// ---- launchers implemented in the kernel sources -------------------------
+// Transforms (FP64 arithmetic); all enqueue on `s`.
+hipError_t launch_project_images(hipStream_t s, const double* spheres, int ns, const double* quats,
+                                 int nq, int nx, int ny, double pixel, double* out_i0);
+hipError_t launch_rdft2(hipStream_t s, const double* real_in, const float* real_in_f32, int n,
+                        int nx, int ny, double2* rows_scratch, double2* spec64);
+hipError_t launch_spec_store(hipStream_t s, const double2* spec64, int n, int nx, int ny,
+                             float2* spec, int32_t* expo);
+hipError_t launch_image_stats(hipStream_t s, const float* imgs, int n, int npix, double* stats);
+hipError_t launch_render(hipStream_t s, const float2* spec, const int32_t* expo, int n, int nx,
+                         int ny, double pixel, const double* ctf, const int32_t* shifts,
+                         const double* norm_offset, const float* noise, double snr,
+                         double2* spec64, double2* cols_scratch, double* i1, float* out);
+
+// Likelihood support.
+hipError_t launch_ctf_table(hipStream_t s, const double* ctf, int nc, int nx, int ny, double pixel,
+                            float* table);
+hipError_t launch_proj_norms(hipStream_t s, const float2* pspec, const int32_t* pexpo, int nq,
+                             const float* table, int nc, int nx, int ny, double* B);
+
+struct LogpostArgs {
+  const float2* ispec; const int32_t* iexpo; const double* istats; int ni;   // image chunk
+  const float2* pspec; const int32_t* pexpo; int nq;                        // all projections
+  const float* table; const double* B; int nc;
+  int nx, ny, S;
+  const int32_t* cand; int k;     // [ni][k] chunk-relative rows, or null
+  bioem_rec* rec;                 // [ni][nq or k]
+};
+hipError_t launch_logpost_f32(hipStream_t s, const LogpostArgs& a);
+size_t f32_smem_bytes(int nx, int ny, int S);
+constexpr size_t kMaxSmem = 160 * 1024;
+hipError_t launch_logpost_split(hipStream_t s, const LogpostArgs& a, bool bf16);
+bool split_supported(int nx, int ny, int S);
+
+hipError_t launch_finalize(hipStream_t s, const bioem_rec* rec, int ni, int nq_eval, int nq_total,
+                           const double* istats, double log_prior, double* logp, bioem_best* best,
+                           double* logp_orient);
+hipError_t launch_best_decode(hipStream_t s, bioem_best* best, int ni, int S);
+
+}  // namespace bioem
+
+// ---- device helpers ---------------------------------------------------------
+#define BIOEM_DEV static __device__ __forceinline__
+
+// exp(2 pi i t / n) in FP64 with the argument reduced exactly (t in [0, n)).
+BIOEM_DEV double2 twiddle64(long t, int n) {
+  double s, c;
+  sincospi(2.0 * (double)t / (double)n, &s, &c);
+  return make_double2(c, s);
+}

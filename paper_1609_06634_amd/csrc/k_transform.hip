@@ -1,0 +1,408 @@
+// Projection of Gaussian-sphere models, half-spectrum DFTs, per-image sums and
+// synthetic maps.  None of this is on the per-evaluation hot loop (it runs
+// once per orientation or per image, Listing 1's outer loops), so it favours
+// accuracy: every step computes in FP64 and only the stored spectra are FP32.
+#include "common.hpp"
+
+namespace bioem {
+
+namespace {
+
+constexpr int kProjRows = 16;      // image rows per projection workgroup
+constexpr int kProjSpheres = 8;    // spheres staged in LDS per step
+constexpr int kProjThreads = 256;
+constexpr int kProjMaxPix = kProjRows * kMaxBox / kProjThreads;
+
+// Integral over one pixel [u - h, u + h] of a unit 1-D Gaussian centred at 0,
+// with erfc used on whichever side keeps the difference free of cancellation.
+BIOEM_DEV double pixel_integral(double u, double h, double inv_s2sig) {
+  const double a = (u - h) * inv_s2sig, b = (u + h) * inv_s2sig;
+  if (a > 0.0) return 0.5 * (erfc(a) - erfc(b));
+  if (b < 0.0) return 0.5 * (erfc(-b) - erfc(-a));
+  return 0.5 * (erf(b) - erf(a));
+}
+
+// Eq. (ideal): I0[k][j] = sum_a w_a Ey_a[k] Ex_a[j] for rotated spheres.
+// grid: (ceil(ny / kProjRows), nq); block: kProjThreads.
+__global__ __launch_bounds__(kProjThreads) void k_project(const double* __restrict__ spheres, int ns,
+                                                          const double* __restrict__ quats, int nx,
+                                                          int ny, double pixel, double* __restrict__ out) {
+  __shared__ double ex[kProjSpheres][kMaxBox];
+  __shared__ double ey[kProjSpheres][kProjRows];
+  __shared__ double rot[9];
+  const int q = blockIdx.y;
+  const int k0 = blockIdx.x * kProjRows;
+  const int tid = threadIdx.x;
+  if (tid == 0) {
+    double w = quats[4 * q + 0], x = quats[4 * q + 1], y = quats[4 * q + 2], z = quats[4 * q + 3];
+    const double inv = 1.0 / sqrt(w * w + x * x + y * y + z * z);
+    w *= inv; x *= inv; y *= inv; z *= inv;
+    // first two rows of the active rotation matrix (z is integrated out)
+    rot[0] = 1 - 2 * (y * y + z * z); rot[1] = 2 * (x * y - w * z); rot[2] = 2 * (x * z + w * y);
+    rot[3] = 2 * (x * y + w * z); rot[4] = 1 - 2 * (x * x + z * z); rot[5] = 2 * (y * z - w * x);
+  }
+  __syncthreads();
+  const int rows = min(kProjRows, ny - k0);
+  const int npix = rows * nx;
+  double acc[kProjMaxPix];
+#pragma unroll
+  for (int r = 0; r < kProjMaxPix; ++r) acc[r] = 0.0;
+  const double h = 0.5 * pixel;
+  for (int a0 = 0; a0 < ns; a0 += kProjSpheres) {
+    const int na = min(kProjSpheres, ns - a0);
+    for (int e = tid; e < na * nx; e += kProjThreads) {
+      const int a = e / nx, j = e - a * nx;
+      const double* sp = spheres + 5 * (a0 + a);
+      const double xr = rot[0] * sp[0] + rot[1] * sp[1] + rot[2] * sp[2];
+      const double inv = 1.0 / (sqrt(2.0) * sp[3]);
+      ex[a][j] = pixel_integral((j - nx / 2) * pixel - xr, h, inv);
+    }
+    for (int e = tid; e < na * rows; e += kProjThreads) {
+      const int a = e / rows, kk = e - a * rows;
+      const double* sp = spheres + 5 * (a0 + a);
+      const double yr = rot[3] * sp[0] + rot[4] * sp[1] + rot[5] * sp[2];
+      const double inv = 1.0 / (sqrt(2.0) * sp[3]);
+      ey[a][kk] = sp[4] * pixel_integral((k0 + kk - ny / 2) * pixel - yr, h, inv);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < kProjMaxPix; ++r) {
+      const int p = tid + r * kProjThreads;
+      if (p < npix) {
+        const int kk = p / nx, j = p - kk * nx;
+        double s = acc[r];
+        for (int a = 0; a < na; ++a) s = fma(ey[a][kk], ex[a][j], s);
+        acc[r] = s;
+      }
+    }
+    __syncthreads();
+  }
+  double* dst = out + ((size_t)q * ny + k0) * nx;
+#pragma unroll
+  for (int r = 0; r < kProjMaxPix; ++r) {
+    const int p = tid + r * kProjThreads;
+    if (p < npix) dst[p] = acc[r];
+  }
+}
+
+// Row pass of the forward 2-D DFT: rows[i][k][m] = sum_j x[i][k][j] e^{-2 pi i m j / nx}.
+// grid: n * ny blocks; block: 128.
+__global__ __launch_bounds__(128) void k_rdft_rows(const double* __restrict__ in64,
+                                                   const float* __restrict__ in32, int nx,
+                                                   double2* __restrict__ rows) {
+  __shared__ double x[kMaxBox];
+  __shared__ double2 tw[kMaxBox];
+  const size_t row = blockIdx.x;
+  const int mh = nx / 2 + 1;
+  for (int j = threadIdx.x; j < nx; j += blockDim.x) {
+    x[j] = in64 ? in64[row * nx + j] : (double)in32[row * nx + j];
+    tw[j] = twiddle64(j, nx);
+  }
+  __syncthreads();
+  for (int m = threadIdx.x; m < mh; m += blockDim.x) {
+    double re = 0.0, im = 0.0;
+    int t = 0;
+    for (int j = 0; j < nx; ++j) {
+      re = fma(x[j], tw[t].x, re);
+      im = fma(-x[j], tw[t].y, im);
+      t += m;
+      if (t >= nx) t -= nx;
+    }
+    rows[row * mh + m] = make_double2(re, im);
+  }
+}
+
+// Column pass: spec[i][m][l] = sum_k rows[i][k][m] e^{-2 pi i l k / ny}.
+// grid: n * mh blocks; block: 128.
+__global__ __launch_bounds__(128) void k_cdft_cols(const double2* __restrict__ rows, int nx, int ny,
+                                                   double2* __restrict__ spec) {
+  __shared__ double2 col[kMaxBox];
+  __shared__ double2 tw[kMaxBox];
+  const int mh = nx / 2 + 1;
+  const size_t item = blockIdx.x / mh;
+  const int m = blockIdx.x - item * mh;
+  for (int k = threadIdx.x; k < ny; k += blockDim.x) {
+    col[k] = rows[(item * ny + k) * mh + m];
+    tw[k] = twiddle64(k, ny);
+  }
+  __syncthreads();
+  for (int l = threadIdx.x; l < ny; l += blockDim.x) {
+    double re = 0.0, im = 0.0;
+    int t = 0;
+    for (int k = 0; k < ny; ++k) {
+      // (a + ib)(c - is) = (ac + bs) + i(bc - as)
+      re = fma(col[k].x, tw[t].x, fma(col[k].y, tw[t].y, re));
+      im = fma(col[k].y, tw[t].x, fma(-col[k].x, tw[t].y, im));
+      t += l;
+      if (t >= ny) t -= ny;
+    }
+    spec[(item * mh + m) * ny + l] = make_double2(re, im);
+  }
+}
+
+// Scale each item's spectrum by 2^-e with e the exponent of its largest
+// magnitude (so all |values| < 1) and store as FP32.  grid: n; block: 256.
+__global__ __launch_bounds__(256) void k_spec_store(const double2* __restrict__ spec64, int len,
+                                                    float2* __restrict__ spec, int32_t* __restrict__ expo) {
+  __shared__ double red[256];
+  const size_t item = blockIdx.x;
+  const double2* src = spec64 + item * len;
+  double mx = 0.0;
+  for (int e = threadIdx.x; e < len; e += 256) mx = fmax(mx, fmax(fabs(src[e].x), fabs(src[e].y)));
+  red[threadIdx.x] = mx;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + w]);
+    __syncthreads();
+  }
+  int ex = 0;
+  if (red[0] > 0.0) frexp(red[0], &ex);
+  if (threadIdx.x == 0) expo[item] = ex;
+  float2* dst = spec + item * len;
+  for (int e = threadIdx.x; e < len; e += 256)
+    dst[e] = make_float2((float)ldexp(src[e].x, -ex), (float)ldexp(src[e].y, -ex));
+}
+
+// Deterministic FP64 block sum over 256 threads.
+BIOEM_DEV double block_sum256(double v, double* red) {
+  red[threadIdx.x] = v;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  const double r = red[0];
+  __syncthreads();
+  return r;
+}
+
+// Per-image C_o, C_oo and A = sum (I - C_o/n)^2 in FP64, two passes.
+__global__ __launch_bounds__(256) void k_image_stats(const float* __restrict__ imgs, int npix,
+                                                     double* __restrict__ stats) {
+  __shared__ double red[256];
+  const float* x = imgs + (size_t)blockIdx.x * npix;
+  double s = 0.0, s2 = 0.0;
+  for (int e = threadIdx.x; e < npix; e += 256) {
+    const double v = x[e];
+    s += v;
+    s2 = fma(v, v, s2);
+  }
+  const double c_o = block_sum256(s, red);
+  const double c_oo = block_sum256(s2, red);
+  const double mean = c_o / npix;
+  double a = 0.0;
+  for (int e = threadIdx.x; e < npix; e += 256) {
+    const double d = (double)x[e] - mean;
+    a = fma(d, d, a);
+  }
+  const double A = block_sum256(a, red);
+  if (threadIdx.x == 0) {
+    stats[3 * blockIdx.x + 0] = c_o;
+    stats[3 * blockIdx.x + 1] = c_oo;
+    stats[3 * blockIdx.x + 2] = A;
+  }
+}
+
+// CTF(s|a,A) Env(s|b) for signed frequencies (m, l), Section 2.
+BIOEM_DEV double ctf_env(double a, double amp, double b, int m, int l, int nx, int ny, double pixel) {
+  const int ls = (l <= ny / 2) ? l : l - ny;
+  const double fx = (double)m / (nx * pixel), fy = (double)ls / (ny * pixel);
+  const double s2 = 4.0 * M_PI * M_PI * (fx * fx + fy * fy);
+  const double ph = 0.5 * a * s2;
+  double sn, cs;
+  sincos(ph, &sn, &cs);
+  return (-amp * cs - sqrt(1.0 - amp * amp) * sn) * exp(-0.5 * b * s2);
+}
+
+// Synthetic map, step 1: spec1[i][m][l] = S_i[m][l] 2^e_i CTF Env (FP64).
+__global__ __launch_bounds__(256) void k_render_filter(const float2* __restrict__ spec,
+                                                       const int32_t* __restrict__ expo, int nx, int ny,
+                                                       double pixel, const double* __restrict__ ctf,
+                                                       double2* __restrict__ out) {
+  const int mh = nx / 2 + 1;
+  const size_t item = blockIdx.y;
+  const int len = mh * ny;
+  const int e = blockIdx.x * 256 + threadIdx.x;
+  if (e >= len) return;
+  const int m = e / ny, l = e - m * ny;
+  const double t = ctf_env(ctf[3 * item], ctf[3 * item + 1], ctf[3 * item + 2], m, l, nx, ny, pixel);
+  const float2 v = spec[item * len + e];
+  const double sc = ldexp(1.0, expo[item]) * t;
+  out[item * len + e] = make_double2(v.x * sc, v.y * sc);
+}
+
+// Inverse column pass: g[i][k][m] = sum_l spec1[i][m][l] e^{+2 pi i l k / ny}.
+__global__ __launch_bounds__(128) void k_icdft_cols(const double2* __restrict__ spec, int nx, int ny,
+                                                    double2* __restrict__ g) {
+  __shared__ double2 col[kMaxBox];
+  __shared__ double2 tw[kMaxBox];
+  const int mh = nx / 2 + 1;
+  const size_t item = blockIdx.x / mh;
+  const int m = blockIdx.x - item * mh;
+  for (int l = threadIdx.x; l < ny; l += blockDim.x) {
+    col[l] = spec[(item * mh + m) * ny + l];
+    tw[l] = twiddle64(l, ny);
+  }
+  __syncthreads();
+  for (int k = threadIdx.x; k < ny; k += blockDim.x) {
+    double re = 0.0, im = 0.0;
+    int t = 0;
+    for (int l = 0; l < ny; ++l) {
+      re = fma(col[l].x, tw[t].x, fma(-col[l].y, tw[t].y, re));
+      im = fma(col[l].y, tw[t].x, fma(col[l].x, tw[t].y, im));
+      t += k;
+      if (t >= ny) t -= ny;
+    }
+    g[(item * ny + k) * mh + m] = make_double2(re, im);
+  }
+}
+
+// Inverse row pass (complex-to-real): i1[i][k][j] = (1/n) sum_m w_m Re(g e^{+2 pi i m j/nx}),
+// w_m = 1 for m = 0 and m = nx/2, else 2 (the Hermitian partner columns).
+__global__ __launch_bounds__(128) void k_icrdft_rows(const double2* __restrict__ g, int nx, int ny,
+                                                     double* __restrict__ i1) {
+  __shared__ double2 row[kMaxBox / 2 + 1];
+  __shared__ double2 tw[kMaxBox];
+  const int mh = nx / 2 + 1;
+  const size_t r = blockIdx.x;
+  for (int m = threadIdx.x; m < mh; m += blockDim.x) row[m] = g[r * mh + m];
+  for (int j = threadIdx.x; j < nx; j += blockDim.x) tw[j] = twiddle64(j, nx);
+  __syncthreads();
+  const double inv_n = 1.0 / ((double)nx * ny);
+  for (int j = threadIdx.x; j < nx; j += blockDim.x) {
+    double acc = 0.0;
+    int t = 0;
+    for (int m = 0; m < mh; ++m) {
+      const double w = (m == 0 || 2 * m == nx) ? 1.0 : 2.0;
+      acc = fma(w, row[m].x * tw[t].x - row[m].y * tw[t].y, acc);
+      t += j;
+      if (t >= nx) t -= nx;
+    }
+    i1[r * nx + j] = acc * inv_n;
+  }
+}
+
+// Synthetic map, last step: shift, scale, offset and noise at the given SNR.
+__global__ __launch_bounds__(256) void k_render_finish(const double* __restrict__ i1, int nx, int ny,
+                                                       const int32_t* __restrict__ shifts,
+                                                       const double* __restrict__ norm_offset,
+                                                       const float* __restrict__ noise, double snr,
+                                                       float* __restrict__ out) {
+  __shared__ double red[256];
+  const size_t item = blockIdx.x;
+  const int npix = nx * ny;
+  const double* x = i1 + item * npix;
+  double s = 0.0;
+  for (int e = threadIdx.x; e < npix; e += 256) s += x[e];
+  const double mean = block_sum256(s, red) / npix;
+  double v = 0.0;
+  for (int e = threadIdx.x; e < npix; e += 256) {
+    const double d = x[e] - mean;
+    v = fma(d, d, v);
+  }
+  const double var = block_sum256(v, red) / npix;
+  const double sigma = noise ? sqrt(var / snr) : 0.0;
+  const int dx = shifts[2 * item], dy = shifts[2 * item + 1];
+  const double N = norm_offset ? norm_offset[2 * item] : 1.0;
+  const double mu = norm_offset ? norm_offset[2 * item + 1] : 0.0;
+  for (int e = threadIdx.x; e < npix; e += 256) {
+    const int k = e / nx, j = e - k * nx;
+    const int ks = ((k + dy) % ny + ny) % ny, js = ((j + dx) % nx + nx) % nx;
+    double val = N * x[ks * nx + js] - mu;
+    if (noise) val += sigma * (double)noise[item * npix + e];
+    out[item * npix + e] = (float)val;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_ctf_table(const double* __restrict__ ctf, int nx, int ny,
+                                                   double pixel, float* __restrict__ table) {
+  const int mh = nx / 2 + 1, len = mh * ny;
+  const int c = blockIdx.y;
+  const int e = blockIdx.x * 256 + threadIdx.x;
+  if (e >= len) return;
+  const int m = e / ny, l = e - m * ny;
+  table[(size_t)c * len + e] = (float)ctf_env(ctf[3 * c], ctf[3 * c + 1], ctf[3 * c + 2], m, l, nx, ny, pixel);
+}
+
+// B_qc = (1/n) sum_{s != 0} w_s |P_q(s) T_c(s)|^2 (Plancherel), FP64.
+// grid: nq * nc blocks; block: 256.
+__global__ __launch_bounds__(256) void k_proj_norms(const float2* __restrict__ pspec,
+                                                    const int32_t* __restrict__ pexpo,
+                                                    const float* __restrict__ table, int nc, int nx,
+                                                    int ny, double* __restrict__ B) {
+  __shared__ double red[256];
+  const int mh = nx / 2 + 1, len = mh * ny;
+  const int q = blockIdx.x / nc, c = blockIdx.x - q * nc;
+  const float2* p = pspec + (size_t)q * len;
+  const float* t = table + (size_t)c * len;
+  double acc = 0.0;
+  for (int e = threadIdx.x; e < len; e += 256) {
+    if (e == 0) continue;
+    const int m = e / ny;
+    const double w = (m == 0 || 2 * m == nx) ? 1.0 : 2.0;
+    const double tt = t[e];
+    const double re = p[e].x * tt, im = p[e].y * tt;
+    acc = fma(w, re * re + im * im, acc);
+  }
+  const double s = block_sum256(acc, red);
+  if (threadIdx.x == 0) B[blockIdx.x] = ldexp(s, 2 * pexpo[q]) / ((double)nx * ny);
+}
+
+}  // namespace
+
+static hipError_t last() { return hipGetLastError(); }
+
+hipError_t launch_project_images(hipStream_t s, const double* spheres, int ns, const double* quats,
+                                 int nq, int nx, int ny, double pixel, double* out_i0) {
+  dim3 grid((ny + kProjRows - 1) / kProjRows, nq);
+  hipLaunchKernelGGL(k_project, grid, dim3(kProjThreads), 0, s, spheres, ns, quats, nx, ny, pixel, out_i0);
+  return last();
+}
+
+hipError_t launch_rdft2(hipStream_t s, const double* real_in, const float* real_in_f32, int n,
+                        int nx, int ny, double2* rows_scratch, double2* spec64) {
+  const int mh = nx / 2 + 1;
+  hipLaunchKernelGGL(k_rdft_rows, dim3(n * ny), dim3(128), 0, s, real_in, real_in_f32, nx, rows_scratch);
+  hipLaunchKernelGGL(k_cdft_cols, dim3(n * mh), dim3(128), 0, s, rows_scratch, nx, ny, spec64);
+  return last();
+}
+
+hipError_t launch_spec_store(hipStream_t s, const double2* spec64, int n, int nx, int ny,
+                             float2* spec, int32_t* expo) {
+  hipLaunchKernelGGL(k_spec_store, dim3(n), dim3(256), 0, s, spec64, (nx / 2 + 1) * ny, spec, expo);
+  return last();
+}
+
+hipError_t launch_image_stats(hipStream_t s, const float* imgs, int n, int npix, double* stats) {
+  hipLaunchKernelGGL(k_image_stats, dim3(n), dim3(256), 0, s, imgs, npix, stats);
+  return last();
+}
+
+hipError_t launch_render(hipStream_t s, const float2* spec, const int32_t* expo, int n, int nx,
+                         int ny, double pixel, const double* ctf, const int32_t* shifts,
+                         const double* norm_offset, const float* noise, double snr,
+                         double2* spec64, double2* cols_scratch, double* i1, float* out) {
+  const int mh = nx / 2 + 1, len = mh * ny;
+  hipLaunchKernelGGL(k_render_filter, dim3((len + 255) / 256, n), dim3(256), 0, s, spec, expo, nx,
+                     ny, pixel, ctf, spec64);
+  hipLaunchKernelGGL(k_icdft_cols, dim3(n * mh), dim3(128), 0, s, spec64, nx, ny, cols_scratch);
+  hipLaunchKernelGGL(k_icrdft_rows, dim3(n * ny), dim3(128), 0, s, cols_scratch, nx, ny, i1);
+  hipLaunchKernelGGL(k_render_finish, dim3(n), dim3(256), 0, s, i1, nx, ny, shifts, norm_offset,
+                     noise, snr, out);
+  return last();
+}
+
+hipError_t launch_ctf_table(hipStream_t s, const double* ctf, int nc, int nx, int ny, double pixel,
+                            float* table) {
+  const int len = (nx / 2 + 1) * ny;
+  hipLaunchKernelGGL(k_ctf_table, dim3((len + 255) / 256, nc), dim3(256), 0, s, ctf, nx, ny, pixel, table);
+  return last();
+}
+
+hipError_t launch_proj_norms(hipStream_t s, const float2* pspec, const int32_t* pexpo, int nq,
+                             const float* table, int nc, int nx, int ny, double* B) {
+  hipLaunchKernelGGL(k_proj_norms, dim3(nq * nc), dim3(256), 0, s, pspec, pexpo, table, nc, nx, ny, B);
+  return last();
+}
+
+}  // namespace bioem

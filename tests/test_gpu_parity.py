@@ -1,0 +1,169 @@
+"""GPU path vs the FP64 oracle, through the C ABI (needs a gfx950 GPU)."""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import oracle as O
+from workloads import make_workload
+
+pytestmark = pytest.mark.gpu
+
+TOL_NAT = 0.01   # per-image |delta log P| bar for the plain path
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def P():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    import paper_1609_06634_amd as P
+    P.load()
+    return P
+
+
+@pytest.fixture(scope="module")
+def ctx(P):
+    return P.Context(0)
+
+
+@pytest.fixture(scope="module")
+def cfg1():
+    wl = make_workload(1)
+    cls = wl.classes[0]
+    imgs = O.render_images(cls, wl.models)
+    return wl, cls, imgs
+
+
+@pytest.fixture(scope="module")
+def cfg1_oracle(cfg1):
+    wl, cls, imgs = cfg1
+    return O.logpost_oracle(imgs, wl.models[0], cls.quats, cls.ctf, cls.pixel_A, cls.max_shift,
+                            method="direct")
+
+
+def test_render_matches_oracle(P, ctx, cfg1):
+    wl, cls, _ = cfg1
+    _say("render: config1 5 images")
+    sel = slice(0, 5)
+    proj = P.project(ctx, wl.models[0], cls.img_quat[sel], cls.nx, cls.ny, cls.pixel_A)
+    norm = np.array([[1.3, 0.4], [0.8, -0.2], [1.0, 0.0], [2.0, 1.0], [0.5, 0.5]])
+    got = P.render(ctx, proj, cls.img_ctf[sel], cls.img_shift[sel], norm_offset=norm)
+    for j, i in enumerate(range(5)):
+        ref = O.render_image(wl.models[0], cls.img_quat[i], cls.img_ctf[i], cls.img_shift[i],
+                             cls.nx, cls.ny, cls.pixel_A, norm[j, 0], norm[j, 1])
+        scale = np.abs(ref).max()
+        assert np.abs(got[j] - ref).max() < 2e-6 * scale, (i, np.abs(got[j] - ref).max(), scale)
+
+
+def test_render_noise_snr(P, ctx, cfg1):
+    wl, cls, _ = cfg1
+    proj = P.project(ctx, wl.models[0], cls.img_quat[:3], cls.nx, cls.ny, cls.pixel_A)
+    noise = cls.noise(0, 3)
+    got = P.render(ctx, proj, cls.img_ctf[:3], cls.img_shift[:3], noise=noise, snr=cls.snr)
+    ref = O.render_images(cls.subset(3), wl.models)
+    assert np.abs(got - ref).max() < 2e-5 * np.abs(ref).max()
+
+
+@pytest.mark.parametrize("prec", ["f32"])
+def test_config1_logpost_parity(P, ctx, cfg1, cfg1_oracle, prec):
+    wl, cls, imgs = cfg1
+    r = cfg1_oracle
+    _say(f"config1 parity prec={prec}: 50 images x 100 q x 4 c, S=5")
+    proj = P.project(ctx, wl.models[0], cls.quats, cls.nx, cls.ny, cls.pixel_A)
+    im = P.prepare_images(ctx, imgs)
+    out = P.logpost(ctx, proj, im, cls.ctf, cls.max_shift, prec=prec, orient=True)
+    d = np.abs(out["logp"] - r.logp)
+    _say(f"  max |dlogP| = {d.max():.3e}")
+    assert d.max() <= TOL_NAT
+    b = out["best"]
+    assert np.all(b["status"] == 0)
+    assert np.abs(b["logl"] - r.best_logl).max() <= TOL_NAT
+    # the maximising grid point is unique here unless two values tie within tolerance
+    same = (b["q"] == r.best_q) & (b["c"] == r.best_c) & (b["dx"] == r.best_dx) & (b["dy"] == r.best_dy)
+    assert same.mean() >= 0.9
+    for i in np.nonzero(~same)[0]:
+        # a different argmax must still attain the maximum within tolerance
+        assert abs(b["logl"][i] - r.best_logl[i]) <= TOL_NAT
+    do = np.abs(out["orient"] - r.logp_orient)
+    assert do.max() <= TOL_NAT
+
+
+def test_recovery_on_grid(P, ctx):
+    wl = make_workload(1, n_images=1)
+    cls = wl.classes[0]
+    rng = np.random.default_rng(21)
+    cases = [(17, 2, (3, -2)), (63, 0, (-4, 1)), (5, 3, (0, 5)), (88, 1, (-5, -5))]
+    imgs = np.array([O.render_image(wl.models[0], cls.quats[q], cls.ctf[c], d, cls.nx, cls.ny,
+                                    cls.pixel_A, 1.0, 0.0, rng.standard_normal((cls.ny, cls.nx)), 10.0)
+                     for q, c, d in cases], dtype=np.float32)
+    proj = P.project(ctx, wl.models[0], cls.quats, cls.nx, cls.ny, cls.pixel_A)
+    out = P.logpost(ctx, proj, P.prepare_images(ctx, imgs), cls.ctf, cls.max_shift)
+    b = out["best"]
+    for i, (q, c, d) in enumerate(cases):
+        assert (b["q"][i], b["c"][i], b["dx"][i], b["dy"][i]) == (q, c, d[0], d[1])
+
+
+def test_ragged_box_and_edges(P, ctx):
+    """Non-square box, S = 0 and S at its maximum, a single CTF, a constant image."""
+    wl = make_workload(1, n_images=4)
+    cls = wl.classes[0]
+    nx, ny, pix = 40, 26, 3.1
+    rng = np.random.default_rng(5)
+    quats = cls.quats[:7]
+    imgs = np.array([O.render_image(wl.models[0], cls.img_quat[i], cls.img_ctf[i], (1, -2), nx, ny,
+                                    pix, 1.0, 0.0, rng.standard_normal((ny, nx)), 0.5)
+                     for i in range(3)] + [np.full((ny, nx), 3.0)], dtype=np.float32)
+    proj = P.project(ctx, wl.models[0], quats, nx, ny, pix)
+    im = P.prepare_images(ctx, imgs)
+    for S, ctf in [(0, cls.ctf[:1]), (3, cls.ctf), (12, cls.ctf[1:3])]:
+        _say(f"ragged box {nx}x{ny} S={S} nc={len(ctf)}")
+        out = P.logpost(ctx, proj, im, ctf, S, orient=True)
+        r = O.logpost_oracle(imgs[:3].astype(np.float64), wl.models[0], quats, ctf, pix, S, method="fft")
+        assert np.abs(out["logp"][:3] - r.logp).max() <= TOL_NAT
+        assert np.abs(out["orient"][:3] - r.logp_orient).max() <= TOL_NAT
+        assert out["best"]["status"][3] == 1 and math.isnan(out["logp"][3])
+        assert np.all(out["best"]["status"][:3] == 0)
+
+
+def test_candidate_subset_matches_oracle(P, ctx, cfg1):
+    wl, cls, imgs = cfg1
+    sub = imgs[:6]
+    rng = np.random.default_rng(3)
+    cand = np.stack([np.sort(rng.choice(100, 12, replace=False)) for _ in range(6)]).astype(np.int32)
+    proj = P.project(ctx, wl.models[0], cls.quats, cls.nx, cls.ny, cls.pixel_A)
+    out = P.logpost(ctx, proj, P.prepare_images(ctx, sub), cls.ctf, cls.max_shift, cand_q=cand, orient=True)
+    for i in range(6):
+        r = O.logpost_oracle(sub[i:i + 1].astype(np.float64), wl.models[0], cls.quats, cls.ctf,
+                             cls.pixel_A, cls.max_shift, method="fft", q_subset=list(cand[i]))
+        assert abs(out["logp"][i] - r.logp[0]) <= TOL_NAT
+        assert out["best"]["q"][i] in set(cand[i].tolist())
+        mask = np.zeros(100, bool)
+        mask[cand[i]] = True
+        assert np.all(np.isneginf(out["orient"][i][~mask]))
+        assert np.abs(out["orient"][i][mask] - r.logp_orient[0][mask]).max() <= TOL_NAT
+
+
+def test_invalid_arguments(P, ctx, cfg1):
+    wl, cls, imgs = cfg1
+    proj = P.project(ctx, wl.models[0], cls.quats[:3], cls.nx, cls.ny, cls.pixel_A)
+    im = P.prepare_images(ctx, imgs[:2])
+    with pytest.raises(P.BioemError) as e:
+        P.logpost(ctx, proj, im, cls.ctf, 32)            # S >= nx/2
+    assert e.value.status == -1
+    bad = cls.ctf.copy()
+    bad[0, 1] = 1.5
+    with pytest.raises(P.BioemError):
+        P.logpost(ctx, proj, im, bad, 2)                  # amplitude contrast > 1
+    with pytest.raises(P.BioemError):
+        P.project(ctx, wl.models[0], cls.quats[:3], 63, 64, cls.pixel_A)   # odd box
+    with pytest.raises(P.BioemError):
+        P.logpost(ctx, proj, im, cls.ctf, 2, cand_q=np.full((2, 1), 7, np.int32))  # q out of range
+    im2 = P.prepare_images(ctx, np.zeros((1, 32, 32), np.float32))
+    with pytest.raises(P.BioemError):
+        P.logpost(ctx, proj, im2, cls.ctf, 2)             # box mismatch
