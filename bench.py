@@ -1,0 +1,179 @@
+#!/usr/bin/env python3
+"""Throughput of the BioEM posterior hot path on one MI355X.
+
+A step is one pass of the whole path over the paper-shaped workload
+(224x224 px at 1.32 A/px, 1000 images, 4608 orientations x 8 CTF sets,
+shifts +-20 px): Fourier projections of the 1500-sphere model over the
+orientation grid, image spectra and sums, and the posterior over every
+(image, orientation, CTF set, shift).  Inputs (model, grids, rendered
+images) are resident in HBM before the timed region starts.
+
+Prints one JSON line (rank 0).  Progress goes to stderr.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import platform
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "posterior evals/s (image×orient×CTF, all shifts) @224² px; |Δlog P| vs FP64"
+
+# Algorithmic work per evaluation at 224^2, S = 20 (pointwise product, pruned
+# inverse transform counted as an FFT, likelihood epilogue): FP32 and FP64 flops.
+ALG_FP32_PER_EVAL = 6 * 224 * 113 + 113 * 5 * 224 * math.log2(224) + 41 * 2.5 * 224 * math.log2(224)
+ALG_FP64_PER_EVAL = 1681 * 45
+PEAK_FP32_TFLOPS = 157.3
+PEAK_FP64_TFLOPS = 78.6
+
+
+def log(msg: str):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def cpu_baseline(sample: str):
+    """Time the FP64 oracle on a bounded sample of the same workload."""
+    import numpy as np
+    import oracle as O
+    from workloads import make_workload
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([t.get("num_threads", 1) for t in threadpool_info()] or [1])
+    except Exception:  # pragma: no cover
+        threads = 1
+    ni, nq, nc = (int(x) for x in sample.split("x"))
+    wl = make_workload(2, n_images=ni)
+    cls = wl.classes[0]
+    imgs = O.render_images(cls, wl.models)
+    t0 = time.perf_counter()
+    O.logpost_oracle(imgs, wl.models[0], cls.quats[:nq], cls.ctf[:nc], cls.pixel_A, cls.max_shift,
+                     method="direct")
+    dt = time.perf_counter() - t0
+    evals = ni * nq * nc
+    cpu = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                cpu = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return {"value": evals / dt, "unit": "evals/s", "cores": threads, "kind": "oracle",
+            "sample": f"{ni} images x {nq} orientations x {nc} CTF sets of the 224^2 workload, "
+                      f"all 1681 shifts, direct FP64 correlation; {dt:.1f} s on {cpu} "
+                      f"(os.cpu_count()={os.cpu_count()})"}
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--prec", default="f32", choices=["f32", "split_f16", "split_bf16"])
+    ap.add_argument("--images", type=int, default=1000)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-sample", default="2x8x2")
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(sharding over orientations or images is described in the design notes)",
+              file=sys.stderr)
+        return 2
+
+    import numpy as np
+    import torch
+    import paper_1609_06634_amd as P
+    from workloads import make_workload
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda", 0)
+    P.load()
+    ctx = P.Context(0)
+
+    # ---- inputs, resident in HBM ------------------------------------------------
+    log("generating the 224^2 workload")
+    wl = make_workload(2, n_images=args.images)
+    cls = wl.classes[0]
+    model = torch.from_numpy(wl.models[0]).to(dev)
+    quats = torch.from_numpy(cls.quats).to(dev)
+    ctf = torch.from_numpy(cls.ctf).to(dev)
+    img_proj = P.project(ctx, torch.from_numpy(wl.models[0]).to(dev),
+                         torch.from_numpy(cls.img_quat).to(dev), cls.nx, cls.ny, cls.pixel_A)
+    images = P.render(ctx, img_proj, torch.from_numpy(cls.img_ctf).to(dev),
+                      torch.from_numpy(cls.img_shift).to(dev),
+                      noise=torch.from_numpy(cls.noise()).to(dev), snr=cls.snr, device_out=True)
+    img_proj.free()
+    torch.cuda.synchronize()
+    ni, nq, nc, S = args.images, len(cls.quats), len(cls.ctf), cls.max_shift
+    evals = ni * nq * nc
+    log(f"inputs ready: {ni} images, {nq} orientations x {nc} CTF sets, S={S}")
+
+    def step():
+        proj = P.project(ctx, model, quats, cls.nx, cls.ny, cls.pixel_A)
+        im = P.prepare_images(ctx, images)
+        out = P.logpost(ctx, proj, im, ctf, S, prec=args.prec, device_out=True)
+        proj.free()
+        im.free()
+        return out
+
+    for w in range(args.warmup):
+        out = step()
+        torch.cuda.synchronize()
+        log(f"warmup {w + 1}/{args.warmup} done")
+    ctx.set_timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        out = step()
+        torch.cuda.synchronize()
+        log(f"step {k + 1}/{args.steps} done")
+    dt = time.perf_counter() - t0
+    kms, launches, kevals = ctx.kernel_time()
+    ctx.set_timing(False)
+    logp = out["logp"].cpu().numpy()
+    assert np.all(np.isfinite(logp)), "non-finite log posterior"
+    ms_step = dt / args.steps * 1e3
+    value = evals / (dt / args.steps)
+
+    # ---- roofline of the main kernel ------------------------------------------
+    per_launch_evals = kevals / max(launches, 1)
+    t_launch = kms / max(launches, 1) * 1e-3
+    fp32_equiv = per_launch_evals * (ALG_FP32_PER_EVAL + 2.0 * ALG_FP64_PER_EVAL)
+    achieved = fp32_equiv / t_launch / 1e12
+    roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP32_TFLOPS,
+                "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_TFLOPS, 4), "traffic": None,
+                "kernel": "k_logpost_f32" if args.prec == "f32" else "k_logpost_split",
+                "kernel_ms_per_launch": round(t_launch * 1e3, 3), "launches": launches,
+                "evals_per_launch": per_launch_evals}
+
+    line = {"metric": METRIC, "value": value, "unit": "evals/s", "n_gpus": 1, "steps": args.steps,
+            "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True,
+            "scaling": "weak", "vs_baseline": None,
+            "dtype": {"f32": "f32 transform, f64 likelihood",
+                      "split_f16": "f16x2 split on MFMA (f32 acc), f64 likelihood",
+                      "split_bf16": "bf16x2 split on MFMA (f32 acc), f64 likelihood"}[args.prec],
+            "data": "synthetic",
+            "config": {"workload": "224x224 px at 1.32 A/px, 1500-sphere model, "
+                                   f"{ni} images x {nq} orientations x {nc} CTF sets, shifts +-{S}",
+                       "images": ni, "orientations": nq, "ctf_sets": nc, "box": cls.nx,
+                       "max_shift": S, "evals_per_step": evals, "prec": args.prec,
+                       "step": "bioem_project + bioem_prepare_images + bioem_logpost"},
+            "roofline": roofline}
+    if not args.no_cpu_baseline:
+        log(f"timing the CPU oracle on a {args.cpu_sample} sample")
+        line["cpu_baseline"] = cpu_baseline(args.cpu_sample)
+    print(json.dumps(line), flush=True)
+    ctx.close()
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -123,7 +123,8 @@ const char* bioem_version(void);
  *   spheres [ns][5] float64: centre x, y, z (A), width sigma (A), weight
  *           (integral of the normalised 3-D Gaussian);
  *   quats   [nq][4] float64 unit quaternions (w, x, y, z);
- *   nx, ny  even box size in pixels (4 <= n <= 1024); pixel_A > 0.
+ *   nx, ny  even box size in pixels (4 <= n <= 512); pixel_A > 0 (kept with
+ *           the handle: it also sets the CTF frequency scale in bioem_logpost).
  * Each projection is I0[k][j] = sum_a w_a Ey_a[k] Ex_a[j] with pixel-box
  * integrals of the rotated Gaussians (FP64), then its half-spectrum DFT,
  * stored on the device.  *out must be released with bioem_free_proj. */
@@ -160,6 +161,16 @@ bioem_status bioem_logpost(bioem_ctx* ctx, const bioem_proj* proj, const bioem_i
 bioem_status bioem_render(bioem_ctx* ctx, const bioem_proj* proj, const double* ctf,
                           const int32_t* shifts, const double* norm_offset, const float* noise,
                           double snr, bioem_mem in_mem, float* out, bioem_mem out_mem);
+
+/* Kernel timing: while enabled, bioem_logpost records HIP events around each
+ * launch of its main (per-evaluation) kernel on the context's stream.
+ * bioem_get_kernel_time waits for those events and returns the summed
+ * duration in milliseconds and the number of launches since timing was last
+ * enabled, plus the number of evaluations (image x orientation x CTF set)
+ * they covered.  bioem_set_timing resets the totals.  Used by benchmarks to
+ * price the kernel against its roofline. */
+bioem_status bioem_set_timing(bioem_ctx* ctx, int32_t enable);
+bioem_status bioem_get_kernel_time(bioem_ctx* ctx, double* ms, int32_t* launches, double* evals);
 
 void bioem_free_proj(bioem_proj* p);
 void bioem_free_imgs(bioem_imgs* p);

@@ -67,6 +67,8 @@ SIGNATURES = [
     ("bioem_proj_info", _I, [_P, ctypes.POINTER(_I), ctypes.POINTER(_I), ctypes.POINTER(_I)]),
     ("bioem_imgs_info", _I, [_P, ctypes.POINTER(_I), ctypes.POINTER(_I), ctypes.POINTER(_I)]),
     ("bioem_ctf_from_physical", _I, [_D, _D, _D, _D, ctypes.POINTER(_D)]),
+    ("bioem_set_timing", _I, [_P, _I]),
+    ("bioem_get_kernel_time", _I, [_P, ctypes.POINTER(_D), ctypes.POINTER(_I), ctypes.POINTER(_D)]),
 ]
 
 
@@ -136,6 +138,16 @@ class Context:
     def check(self, st: int):
         if st != BIOEM_OK:
             raise BioemError(st, self._lib.bioem_last_error(self.h).decode())
+
+    def set_timing(self, enable: bool = True):
+        self.check(self._lib.bioem_set_timing(self.h, 1 if enable else 0))
+
+    def kernel_time(self):
+        """(ms, launches, evals) of the main kernel in the last logpost call."""
+        ms, n, ev = ctypes.c_double(), ctypes.c_int32(), ctypes.c_double()
+        self.check(self._lib.bioem_get_kernel_time(self.h, ctypes.byref(ms), ctypes.byref(n),
+                                                   ctypes.byref(ev)))
+        return ms.value, n.value, ev.value
 
     def close(self):
         if getattr(self, "h", None):

@@ -127,6 +127,8 @@ bioem_status bioem_create(int device, void* hip_stream, bioem_ctx** out) {
 void bioem_destroy(bioem_ctx* ctx) {
   if (!ctx) return;
   (void)hipSetDevice(ctx->device);
+  for (auto e : ctx->ev_start) (void)hipEventDestroy(e);
+  for (auto e : ctx->ev_stop) (void)hipEventDestroy(e);
   if (ctx->own_stream && ctx->stream) {
     (void)hipStreamSynchronize(ctx->stream);
     (void)hipStreamDestroy(ctx->stream);
@@ -135,6 +137,30 @@ void bioem_destroy(bioem_ctx* ctx) {
 }
 
 const char* bioem_last_error(const bioem_ctx* ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+bioem_status bioem_set_timing(bioem_ctx* ctx, int32_t enable) {
+  if (!ctx) return BIOEM_EINVAL;
+  ctx->timing = enable != 0;
+  ctx->ev_used = 0;
+  ctx->timed_evals = 0.0;
+  return BIOEM_OK;
+}
+
+bioem_status bioem_get_kernel_time(bioem_ctx* ctx, double* ms, int32_t* launches, double* evals) {
+  if (!ctx) return BIOEM_EINVAL;
+  HIP_OR_FAIL(ctx, hipSetDevice(ctx->device));
+  double total = 0.0;
+  for (int i = 0; i < ctx->ev_used; ++i) {
+    HIP_OR_FAIL(ctx, hipEventSynchronize(ctx->ev_stop[i]));
+    float t = 0.f;
+    HIP_OR_FAIL(ctx, hipEventElapsedTime(&t, ctx->ev_start[i], ctx->ev_stop[i]));
+    total += t;
+  }
+  if (ms) *ms = total;
+  if (launches) *launches = ctx->ev_used;
+  if (evals) *evals = ctx->timed_evals;
+  return BIOEM_OK;
+}
 
 void bioem_free_proj(bioem_proj* p) {
   if (!p) return;
@@ -425,6 +451,16 @@ bioem_status bioem_logpost(bioem_ctx* ctx, const bioem_proj* proj, const bioem_i
   HIP_OR_FAIL(ctx, rec.alloc(sizeof(bioem_rec) * (size_t)chunk * nslots));
   const int W = 2 * max_shift + 1;
   const double log_prior = -std::log((double)nq) - std::log((double)nc) - std::log((double)W * W);
+  const int nchunks = (ni + chunk - 1) / chunk;
+  if (ctx->timing) {
+    while ((int)ctx->ev_start.size() < ctx->ev_used + nchunks) {
+      hipEvent_t a, b;
+      HIP_OR_FAIL(ctx, hipEventCreate(&a));
+      HIP_OR_FAIL(ctx, hipEventCreate(&b));
+      ctx->ev_start.push_back(a);
+      ctx->ev_stop.push_back(b);
+    }
+  }
   for (int i0 = 0; i0 < ni; i0 += chunk) {
     const int cn = std::min(chunk, ni - i0);
     LogpostArgs a{};
@@ -434,7 +470,13 @@ bioem_status bioem_logpost(bioem_ctx* ctx, const bioem_proj* proj, const bioem_i
     a.nx = nx; a.ny = ny; a.S = max_shift;
     a.cand = o.cand_q ? dcand.as<int32_t>() + (size_t)i0 * o.k : nullptr; a.k = o.k;
     a.rec = rec.as<bioem_rec>();
+    if (ctx->timing) HIP_OR_FAIL(ctx, hipEventRecord(ctx->ev_start[ctx->ev_used], s));
     hipError_t e = split ? launch_logpost_split(s, a, o.prec == BIOEM_PREC_SPLIT_BF16) : launch_logpost_f32(s, a);
+    if (ctx->timing && e == hipSuccess) {
+      HIP_OR_FAIL(ctx, hipEventRecord(ctx->ev_stop[ctx->ev_used], s));
+      ++ctx->ev_used;
+      ctx->timed_evals += (double)cn * nslots * nc;
+    }
     if (e == hipSuccess)
       e = launch_finalize(s, a.rec, cn, nslots, nq, a.istats, log_prior, d_logp ? d_logp + i0 : nullptr,
                           d_best ? d_best + i0 : nullptr, d_orient ? d_orient + (size_t)i0 * nq : nullptr);

@@ -8,11 +8,18 @@
 
 #include "../../include/bioem.h"
 
+#include <vector>
+
 struct bioem_ctx {
   int device = 0;
   hipStream_t stream = nullptr;
   bool own_stream = false;
   std::string err;
+  // optional timing of the main kernel launches of the last bioem_logpost
+  bool timing = false;
+  std::vector<hipEvent_t> ev_start, ev_stop;
+  int ev_used = 0;
+  double timed_evals = 0.0;
 };
 
 // Half spectra are stored column-major per item: spec[item][m][l] with
