@@ -470,6 +470,7 @@ bioem_status bioem_logpost(bioem_ctx* ctx, const bioem_proj* proj, const bioem_i
     a.nx = nx; a.ny = ny; a.S = max_shift;
     a.cand = o.cand_q ? dcand.as<int32_t>() + (size_t)i0 * o.k : nullptr; a.k = o.k;
     a.rec = rec.as<bioem_rec>();
+    a.ctf = dctf.as<double>(); a.pixel = proj->pixel;
     if (ctx->timing) HIP_OR_FAIL(ctx, hipEventRecord(ctx->ev_start[ctx->ev_used], s));
     hipError_t e = split ? launch_logpost_split(s, a, o.prec == BIOEM_PREC_SPLIT_BF16) : launch_logpost_f32(s, a);
     if (ctx->timing && e == hipSuccess) {

@@ -83,6 +83,8 @@ struct LogpostArgs {
   int nx, ny, S;
   const int32_t* cand; int k;     // [ni][k] chunk-relative rows, or null
   bioem_rec* rec;                 // [ni][nq or k]
+  const double* ctf;              // [nc][3] (a, A, b) on the device
+  double pixel;                   // A per pixel
 };
 hipError_t launch_logpost_f32(hipStream_t s, const LogpostArgs& a);
 size_t f32_smem_bytes(int nx, int ny, int S);
