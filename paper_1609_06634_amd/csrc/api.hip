@@ -3,6 +3,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <vector>
@@ -14,7 +15,7 @@ using namespace bioem;
 namespace {
 
 constexpr size_t kScratchBudget = size_t(256) << 20;   // per transform chunk
-constexpr size_t kRecordBudget = size_t(512) << 20;    // per posterior image chunk
+constexpr size_t kRecordBudget = size_t(1) << 30;      // per posterior image chunk
 
 bioem_status fail(bioem_ctx* ctx, bioem_status st, const char* fmt, ...) {
   if (ctx) {
@@ -90,6 +91,17 @@ bool valid_box(int nx, int ny) {
 }
 
 // Items per transform chunk so that the FP64 scratch stays within budget.
+// Launch shape of the split kernel: BIOEM_SPLIT_SHAPE overrides the default.
+int split_shape_for(bioem_ctx* ctx, int nx, int ny, int S, int nc) {
+  (void)ctx; (void)nx; (void)ny; (void)S; (void)nc;
+  const char* env = std::getenv("BIOEM_SPLIT_SHAPE");
+  if (env) {
+    const int v = std::atoi(env);
+    if (v >= 0 && v < split_num_shapes()) return v;
+  }
+  return 0;
+}
+
 int chunk_items(int n, size_t per_item) {
   size_t c = kScratchBudget / (per_item ? per_item : 1);
   if (c < 1) c = 1;
@@ -242,16 +254,16 @@ bioem_status bioem_project(bioem_ctx* ctx, const double* spheres, int32_t ns, co
   HIP_OR_FAIL(ctx, dq.set(hq.data(), hq.size() * 8, BIOEM_MEM_HOST, s));
 
   const int mh = nx / 2 + 1;
-  const size_t len = (size_t)mh * ny;
+  const size_t len = (size_t)mh * ny, slen = (size_t)mh * spec_ld(ny);
   bioem_proj* p = new (std::nothrow) bioem_proj;
   if (!p) return fail(ctx, BIOEM_ENOMEM, "bioem_project: host allocation");
   p->n = nq; p->nx = nx; p->ny = ny; p->pixel = pixel_A; p->device = ctx->device;
-  hipError_t e = hipMalloc(reinterpret_cast<void**>(&p->spec), sizeof(float2) * len * nq);
+  hipError_t e = hipMalloc(reinterpret_cast<void**>(&p->spec), sizeof(float2) * slen * nq);
   if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&p->expo), sizeof(int32_t) * nq);
   if (e != hipSuccess) {
     bioem_free_proj(p);
     return fail(ctx, BIOEM_ENOMEM, "bioem_project: device allocation of %zu MB failed",
-                (sizeof(float2) * len * nq) >> 20);
+                (sizeof(float2) * slen * nq) >> 20);
   }
   const size_t per = (size_t)nx * ny * 8 + (size_t)ny * mh * 16 + len * 16;
   const int chunk = chunk_items(nq, per);
@@ -264,7 +276,7 @@ bioem_status bioem_project(bioem_ctx* ctx, const double* spheres, int32_t ns, co
     e = launch_project_images(s, dsp.as<double>(), ns, dq.as<double>() + 4 * (size_t)q0, cn, nx, ny,
                               pixel_A, i0.as<double>());
     if (e == hipSuccess) e = launch_rdft2(s, i0.as<double>(), nullptr, cn, nx, ny, rows.as<double2>(), s64.as<double2>());
-    if (e == hipSuccess) e = launch_spec_store(s, s64.as<double2>(), cn, nx, ny, p->spec + len * q0, p->expo + q0);
+    if (e == hipSuccess) e = launch_spec_store(s, s64.as<double2>(), cn, nx, ny, p->spec + slen * q0, p->expo + q0);
   }
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   if (e != hipSuccess) {
@@ -288,11 +300,11 @@ bioem_status bioem_prepare_images(bioem_ctx* ctx, const float* imgs, int32_t ni,
   HIP_OR_FAIL(ctx, hipSetDevice(ctx->device));
   hipStream_t s = ctx->stream;
   const int mh = nx / 2 + 1;
-  const size_t len = (size_t)mh * ny, npix = (size_t)nx * ny;
+  const size_t len = (size_t)mh * ny, slen = (size_t)mh * spec_ld(ny), npix = (size_t)nx * ny;
   bioem_imgs* p = new (std::nothrow) bioem_imgs;
   if (!p) return fail(ctx, BIOEM_ENOMEM, "bioem_prepare_images: host allocation");
   p->n = ni; p->nx = nx; p->ny = ny; p->device = ctx->device;
-  hipError_t e = hipMalloc(reinterpret_cast<void**>(&p->spec), sizeof(float2) * len * ni);
+  hipError_t e = hipMalloc(reinterpret_cast<void**>(&p->spec), sizeof(float2) * slen * ni);
   if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&p->expo), sizeof(int32_t) * ni);
   if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&p->stats), sizeof(double) * 3 * ni);
   if (e != hipSuccess) {
@@ -314,7 +326,7 @@ bioem_status bioem_prepare_images(bioem_ctx* ctx, const float* imgs, int32_t ni,
     }
     if (e == hipSuccess) e = launch_image_stats(s, src, cn, (int)npix, p->stats + 3 * (size_t)i0);
     if (e == hipSuccess) e = launch_rdft2(s, nullptr, src, cn, nx, ny, rows.as<double2>(), s64.as<double2>());
-    if (e == hipSuccess) e = launch_spec_store(s, s64.as<double2>(), cn, nx, ny, p->spec + len * i0, p->expo + i0);
+    if (e == hipSuccess) e = launch_spec_store(s, s64.as<double2>(), cn, nx, ny, p->spec + slen * i0, p->expo + i0);
     if (e == hipSuccess && in_mem == BIOEM_MEM_HOST) e = hipStreamSynchronize(s);  // stage reuse
   }
   if (e == hipSuccess) e = hipStreamSynchronize(s);
@@ -338,7 +350,7 @@ bioem_status bioem_render(bioem_ctx* ctx, const bioem_proj* proj, const double* 
   HIP_OR_FAIL(ctx, hipSetDevice(ctx->device));
   hipStream_t s = ctx->stream;
   const int n = proj->n, nx = proj->nx, ny = proj->ny, mh = nx / 2 + 1;
-  const size_t len = (size_t)mh * ny, npix = (size_t)nx * ny;
+  const size_t len = (size_t)mh * ny, slen = (size_t)mh * spec_ld(ny), npix = (size_t)nx * ny;
   std::vector<double> hc;
   HIP_OR_FAIL(ctx, to_host(ctf, (size_t)n * 3, in_mem, s, hc));
   if (!finite_all(hc.data(), hc.size())) return fail(ctx, BIOEM_EINVAL, "bioem_render: non-finite CTF value");
@@ -364,7 +376,7 @@ bioem_status bioem_render(bioem_ctx* ctx, const bioem_proj* proj, const double* 
   if (e == hipSuccess) e = i1.alloc((size_t)chunk * npix * 8);
   for (int i0 = 0; e == hipSuccess && i0 < n; i0 += chunk) {
     const int cn = std::min(chunk, n - i0);
-    e = launch_render(s, proj->spec + len * i0, proj->expo + i0, cn, nx, ny, proj->pixel,
+    e = launch_render(s, proj->spec + slen * i0, proj->expo + i0, cn, nx, ny, proj->pixel,
                       dc.as<double>() + 3 * (size_t)i0, dsh.as<int32_t>() + 2 * (size_t)i0,
                       dno.d ? dno.as<double>() + 2 * (size_t)i0 : nullptr,
                       dnz.d ? dnz.as<float>() + npix * i0 : nullptr, snr, s64.as<double2>(),
@@ -424,7 +436,7 @@ bioem_status bioem_logpost(bioem_ctx* ctx, const bioem_proj* proj, const bioem_i
         return fail(ctx, BIOEM_EINVAL, "bioem_logpost: candidate %zu = %d outside [0, %d)", e, hcand[e], nq);
   }
   const int mh = nx / 2 + 1;
-  const size_t len = (size_t)mh * ny;
+  const size_t len = (size_t)mh * spec_ld(ny);   // stored spectrum / table stride
   DevIn dctf, dcand;
   HIP_OR_FAIL(ctx, dctf.set(hc.data(), hc.size() * 8, BIOEM_MEM_HOST, s));
   if (o.cand_q) HIP_OR_FAIL(ctx, dcand.set(hcand.data(), hcand.size() * 4, BIOEM_MEM_HOST, s));
@@ -446,9 +458,11 @@ bioem_status bioem_logpost(bioem_ctx* ctx, const bioem_proj* proj, const bioem_i
     if (o.logp_orient) { HIP_OR_FAIL(ctx, dorient.alloc(8 * (size_t)ni * nq)); d_orient = dorient.as<double>(); }
   }
   const int nslots = o.cand_q ? o.k : nq;
-  const int chunk = (int)std::max<size_t>(1, std::min<size_t>(ni, kRecordBudget / (sizeof(bioem_rec) * (size_t)nslots)));
+  const int shape = split ? split_shape_for(ctx, nx, ny, max_shift, nc) : 0;
+  const size_t per_image = sizeof(bioem_erec) * (size_t)nslots * nc;
+  const int chunk = (int)std::max<size_t>(1, std::min<size_t>(ni, kRecordBudget / per_image));
   DevMem rec;
-  HIP_OR_FAIL(ctx, rec.alloc(sizeof(bioem_rec) * (size_t)chunk * nslots));
+  HIP_OR_FAIL(ctx, rec.alloc(per_image * chunk));
   const int W = 2 * max_shift + 1;
   const double log_prior = -std::log((double)nq) - std::log((double)nc) - std::log((double)W * W);
   const int nchunks = (ni + chunk - 1) / chunk;
@@ -467,23 +481,31 @@ bioem_status bioem_logpost(bioem_ctx* ctx, const bioem_proj* proj, const bioem_i
     a.ispec = imgs->spec + len * i0; a.iexpo = imgs->expo + i0; a.istats = imgs->stats + 3 * (size_t)i0; a.ni = cn;
     a.pspec = proj->spec; a.pexpo = proj->expo; a.nq = nq;
     a.table = table.as<float>(); a.B = B.as<double>(); a.nc = nc;
-    a.nx = nx; a.ny = ny; a.S = max_shift;
+    a.nx = nx; a.ny = ny; a.S = max_shift; a.ldy = spec_ld(ny);
     a.cand = o.cand_q ? dcand.as<int32_t>() + (size_t)i0 * o.k : nullptr; a.k = o.k;
-    a.rec = rec.as<bioem_rec>();
-    a.ctf = dctf.as<double>(); a.pixel = proj->pixel;
+    a.rec = rec.as<bioem_erec>();
+    a.kscale = 1.0 / ((double)nx * ny * (double)nx * ny);
     if (ctx->timing) HIP_OR_FAIL(ctx, hipEventRecord(ctx->ev_start[ctx->ev_used], s));
-    hipError_t e = split ? launch_logpost_split(s, a, o.prec == BIOEM_PREC_SPLIT_BF16) : launch_logpost_f32(s, a);
+    hipError_t e = split ? launch_logpost_split(s, a, o.prec == BIOEM_PREC_SPLIT_BF16, shape) : launch_logpost_f32(s, a);
     if (ctx->timing && e == hipSuccess) {
       HIP_OR_FAIL(ctx, hipEventRecord(ctx->ev_stop[ctx->ev_used], s));
       ++ctx->ev_used;
       ctx->timed_evals += (double)cn * nslots * nc;
     }
-    if (e == hipSuccess)
-      e = launch_finalize(s, a.rec, cn, nslots, nq, a.istats, log_prior, d_logp ? d_logp + i0 : nullptr,
-                          d_best ? d_best + i0 : nullptr, d_orient ? d_orient + (size_t)i0 * nq : nullptr);
+    if (e == hipSuccess) {
+      FinalizeArgs f{};
+      f.rec = a.rec; f.ni = cn; f.nslots = nslots; f.nc = nc; f.nq_total = nq; f.nx = nx; f.ny = ny;
+      f.S = max_shift; f.cand = a.cand; f.k = o.k;
+      f.istats = a.istats; f.iexpo = a.iexpo; f.pexpo = proj->expo; f.B = a.B;
+      f.log_prior = log_prior;
+      f.logp = d_logp ? d_logp + i0 : nullptr;
+      f.best = d_best ? d_best + i0 : nullptr;
+      f.orient = d_orient ? d_orient + (size_t)i0 * nq : nullptr;
+      e = launch_finalize(s, f);
+      if (e == hipSuccess && split && f.best) e = launch_best_shift(s, a, f.best);
+    }
     if (e != hipSuccess) return fail(ctx, BIOEM_EDEVICE, "bioem_logpost: launch failed: %s", hipGetErrorString(e));
   }
-  if (d_best) HIP_OR_FAIL(ctx, launch_best_decode(s, d_best, ni, max_shift));
   if (host_out) {
     if (logp) HIP_OR_FAIL(ctx, hipMemcpyAsync(logp, d_logp, 8 * (size_t)ni, hipMemcpyDeviceToHost, s));
     if (best) HIP_OR_FAIL(ctx, hipMemcpyAsync(best, d_best, sizeof(bioem_best) * (size_t)ni, hipMemcpyDeviceToHost, s));

@@ -23,32 +23,36 @@ struct bioem_ctx {
 };
 
 // Half spectra are stored column-major per item: spec[item][m][l] with
-// m in [0, nx/2] (x frequency) and l in [0, ny) (y frequency), scaled by
+// m in [0, nx/2] (x frequency) and l in [0, ny) (y frequency), each column
+// zero-padded to spec_ld(ny) rows, scaled by
 // 2^-expo[item] so that every |value| <= 1 (the split-precision kernels need
 // a bounded range; the scale is undone in FP64 in the likelihood epilogue).
 struct bioem_proj {
   int32_t n = 0, nx = 0, ny = 0;
   double pixel = 0.0;         // A per pixel (sets the CTF frequency scale)
-  float2* spec = nullptr;     // [n][nx/2+1][ny]
+  float2* spec = nullptr;     // [n][nx/2+1][spec_ld(ny)]
   int32_t* expo = nullptr;    // [n]
   int device = 0;
 };
 
 struct bioem_imgs {
   int32_t n = 0, nx = 0, ny = 0;
-  float2* spec = nullptr;     // [n][nx/2+1][ny]
+  float2* spec = nullptr;     // [n][nx/2+1][spec_ld(ny)]
   int32_t* expo = nullptr;    // [n]
   double* stats = nullptr;    // [n][3]: C_o, C_oo, A
   int device = 0;
 };
 
-// Per (image, evaluated orientation) partial result of the main kernels.
-struct bioem_rec {
-  double lse;     // ln sum over CTF sets and shifts of exp(l)
-  double bestl;   // max l over CTF sets and shifts
-  int32_t q;      // orientation index
-  int32_t c;      // CTF index of the maximum
-  int32_t d;      // (dy+S)*(2S+1) + (dx+S) of the maximum
+// Per-evaluation (image, orientation, CTF set) result of the main kernels,
+// in the scaled units of the stored spectra:
+//   x2max = max over the shift window of X(d)^2,
+//   srel  = sum over the window of exp(l(d) - l(d_max)), in [1, W^2],
+//   d     = (dy+S)*(2S+1) + (dx+S) of the maximum (lowest index on ties).
+// The FP64 likelihood terms are added by the finalisation kernel.
+struct bioem_erec {
+  float x2max;
+  float srel;
+  int32_t d;
   int32_t pad;
 };
 
@@ -80,27 +84,39 @@ struct LogpostArgs {
   const float2* ispec; const int32_t* iexpo; const double* istats; int ni;   // image chunk
   const float2* pspec; const int32_t* pexpo; int nq;                        // all projections
   const float* table; const double* B; int nc;
-  int nx, ny, S;
+  int nx, ny, S, ldy;              // ldy = spec_ld(ny)
   const int32_t* cand; int k;     // [ni][k] chunk-relative rows, or null
-  bioem_rec* rec;                 // [ni][nq or k]
-  const double* ctf;              // [nc][3] (a, A, b) on the device
-  double pixel;                   // A per pixel
+  bioem_erec* rec;                // [ni][nq or k][nc]
+  double kscale;                  // (2^e_i 2^e_q / n)^2 kappa factor: 1 / n^2
 };
 hipError_t launch_logpost_f32(hipStream_t s, const LogpostArgs& a);
+// Recompute the argmax displacement (FP32 transform) of best[i]'s (q, c).
+hipError_t launch_best_shift(hipStream_t s, const LogpostArgs& a, bioem_best* best);
 size_t f32_smem_bytes(int nx, int ny, int S);
 constexpr size_t kMaxSmem = 160 * 1024;
-hipError_t launch_logpost_split(hipStream_t s, const LogpostArgs& a, bool bf16);
+hipError_t launch_logpost_split(hipStream_t s, const LogpostArgs& a, bool bf16, int shape);
+int split_num_shapes();
 bool split_supported(int nx, int ny, int S);
 
-hipError_t launch_finalize(hipStream_t s, const bioem_rec* rec, int ni, int nq_eval, int nq_total,
-                           const double* istats, double log_prior, double* logp, bioem_best* best,
-                           double* logp_orient);
-hipError_t launch_best_decode(hipStream_t s, bioem_best* best, int ni, int S);
+// Per image: FP64 likelihood terms from the per-evaluation records, LSE over
+// orientations, CTF sets and shifts, best grid point, per-orientation LSE.
+struct FinalizeArgs {
+  const bioem_erec* rec; int ni, nslots, nc, nq_total, nx, ny, S;
+  const int32_t* cand; int k;     // [ni][k] chunk-relative, or null
+  const double* istats; const int32_t* iexpo; const int32_t* pexpo; const double* B;
+  double log_prior;
+  double* logp; bioem_best* best; double* orient;
+};
+hipError_t launch_finalize(hipStream_t s, const FinalizeArgs& f);
 
 }  // namespace bioem
 
 // ---- device helpers ---------------------------------------------------------
 #define BIOEM_DEV static __device__ __forceinline__
+
+// Stored spectrum columns (and CTF table columns) are padded with zeros to a
+// multiple of 32 rows, the K-step of the matrix-core transform.
+__host__ __device__ static inline int spec_ld(int ny) { return (ny + 31) & ~31; }
 
 // exp(2 pi i t / n) in FP64 with the argument reduced exactly (t in [0, n)).
 BIOEM_DEV double2 twiddle64(long t, int n) {

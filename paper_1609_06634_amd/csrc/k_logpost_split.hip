@@ -24,161 +24,118 @@
 // 22 (16) significant bits with FP32 accumulation.  Spectra are stored
 // scaled so |value| <= 1 (fp16 range); the scale returns in the FP64 terms.
 //
-// Likelihood epilogue (per image, orientation, CTF set): with rho^2(d) =
-// X(d)^2 kappa, the reference value at the window maximum
-//   l_ref = lgamma(n/2-1) - ln 2 - ln(n)/2 + (1-n/2) ln(pi A) - ln(B)/2
-//           + (1-n/2) log1p(-rho^2_max)
-// is FP64, and the shift sum is taken relative to it,
-//   sum_d exp(l(d) - l_ref) = sum_d (1 + u_d)^-(n/2-1),
+// Shift-window epilogue (per image, orientation, CTF set): with rho^2(d) =
+// X(d)^2 kappa and the window maximum rho^2_max, the shift sum relative to
+// the maximising shift is
+//   sum_d exp(l(d) - l_max) = sum_d (1 + u_d)^-(n/2-1),
 //   u_d = (rho^2_max - rho^2(d)) / (1 - rho^2_max) >= 0,
-// where every term lies in (0, 1] and the maximum term is exactly 1, so the
-// sum needs only FP32.  LSE merges across CTF sets are FP64.
+// where every term lies in (0, 1] and the maximum term is exactly 1, so FP32
+// suffices.  When n/2-1 >= 1024, terms with u >= 0.05 are below e^-50 and
+// log1p(u) is a degree-5 series on [0, 0.05] (error below u^6/6).  Each
+// evaluation leaves (max X^2, relative sum); the FP64 likelihood constants,
+// log-sum-exp merges and the best grid point are taken at finalisation, and
+// the best displacement of each image is recovered afterwards.
 //
-// Work decomposition: a wave owns one (image, orientation) pair and loops
-// over CTF sets in groups of EW, sharing the image/projection loads and the
-// stage-1 DFT fragments (LDS) across the group.  Waves are persistent and
-// walk a tiled (image, orientation) order so that concurrently running
-// waves share spectra in L2 and the last-level cache.
+// Work decomposition: a wave owns one (image, orientation, group of EW CTF
+// sets) item and shares the image/projection loads and the stage-1 DFT
+// fragments (LDS) across the group.  Consecutive waves take the other CTF
+// groups of the same (image, orientation), so their spectrum loads meet in
+// L1; items walk a tiled (image, orientation) order so that concurrently
+// running waves share spectra in L2 and the last-level cache.
 #include <algorithm>
 
 #include "common.hpp"
+#include "split_common.hpp"
 
 namespace bioem {
 
 namespace {
 
-typedef _Float16 h8 __attribute__((ext_vector_type(8)));
-typedef __bf16 b8 __attribute__((ext_vector_type(8)));
-typedef float f4 __attribute__((ext_vector_type(4)));
-
-template <bool BF> struct Prec;
-template <> struct Prec<false> {
-  using E = _Float16;
-  using V = h8;
-  static __device__ __forceinline__ f4 mma(V a, V b, f4 c) {
-    return __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, c, 0, 0, 0);
-  }
-};
-template <> struct Prec<true> {
-  using E = __bf16;
-  using V = b8;
-  static __device__ __forceinline__ f4 mma(V a, V b, f4 c) {
-    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
-  }
-};
-
-constexpr int kWaves = 4;
-constexpr int kThreads = 64 * kWaves;
 constexpr int kTileImages = 16;     // item tiling for cache reuse
 constexpr int kTileSlots = 128;
+
+using namespace split;
 
 struct SplitArgs {
   LogpostArgs a;
   const uint4* F;       // stage-1 DFT fragments  [KS][NT][2][64]
   const uint4* G;       // stage-2 DFT fragments  [MT][NT][2][64]
-  const float2* u;      // [nc][nx/2+1]  kappa e^{i phi_m} env_m
-  const float2* v;      // [nc][ny]      e^{i phi_l} env_l
   int KS, MT;
+  int ncg;              // CTF groups per (image, orientation)
   int n_ti, n_ts;       // item tiles along images and slots
 };
 
-template <bool BF>
-__device__ __forceinline__ void split8(const float (&x)[8], typename Prec<BF>::V& hi,
-                                       typename Prec<BF>::V& lo) {
-  using E = typename Prec<BF>::E;
+// Per-lane operands of one stage-1 K-step: the image and projection values of
+// this lane's slot column and the CTF values of each CTF set of the group.
+template <int EW>
+struct Step {
+  float2 o[8], p[8];
+  float t[EW][8];
+};
+
+template <int EW>
+__device__ __forceinline__ void load_step(Step<EW>& st, const float2* Oc, const float2* Pc,
+                                          const float* const (&Tc)[EW], int l0) {
+  load8c(Oc, l0, st.o);
+  load8c(Pc, l0, st.p);
 #pragma unroll
-  for (int r = 0; r < 8; ++r) {
-    const E h = (E)x[r];
-    hi[r] = h;
-    lo[r] = (E)(x[r] - (float)h);
-  }
+  for (int e = 0; e < EW; ++e) load8r(Tc[e], l0, st.t[e]);
 }
 
-// Eight consecutive complex values of one spectrum column, zero past ny.
-__device__ __forceinline__ void load8(const float2* __restrict__ col, int l0, int ny, float2 (&o)[8]) {
-  if (l0 + 8 <= ny) {
-    const float4* p = reinterpret_cast<const float4*>(col + l0);
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const float4 t = p[r];
-      o[2 * r] = make_float2(t.x, t.y);
-      o[2 * r + 1] = make_float2(t.z, t.w);
-    }
-  } else {
-#pragma unroll
-    for (int r = 0; r < 8; ++r) o[r] = (l0 + r < ny) ? col[l0 + r] : make_float2(0.f, 0.f);
-  }
-}
-
-__device__ __forceinline__ float wave_max_f(float v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, 64));
-  return v;
-}
-
-__device__ __forceinline__ double wave_sum_d(double v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-  return v;
-}
-
-__device__ __forceinline__ int wave_min_i(int v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v = min(v, __shfl_xor(v, o, 64));
-  return v;
-}
-
-// log(1 + u) for u >= 0 with relative accuracy near FP32 epsilon (the
-// rounding of 1 + u is compensated by u / ((1 + u) - 1)).
-__device__ __forceinline__ float log1p_acc(float u) {
-  const float w = 1.0f + u;
-  const float d = w - 1.0f;
-  return d == 0.0f ? u : __logf(w) * (u / d);
-}
-
-template <bool BF, int NT, int EW>
-__global__ __launch_bounds__(kThreads, 1) void k_logpost_split(SplitArgs sa) {
+template <bool BF, int NT, int EW, int WAVES, bool PF>
+__global__ __launch_bounds__(64 * WAVES, 1) void k_logpost_split(SplitArgs sa) {
   using P = Prec<BF>;
   using V = typename P::V;
   extern __shared__ uint4 lds[];
   const LogpostArgs& a = sa.a;
   const int KS = sa.KS, MT = sa.MT;
   const int nF = KS * NT * 2 * 64, nG = MT * NT * 2 * 64;
-  for (int e = threadIdx.x; e < nF + nG; e += kThreads) lds[e] = e < nF ? sa.F[e] : sa.G[e - nF];
+  for (int e = threadIdx.x; e < nF + nG; e += 64 * WAVES) lds[e] = e < nF ? sa.F[e] : sa.G[e - nF];
   __syncthreads();
   const uint4* Fs = lds;
   const uint4* Gs = lds + nF;
 
   const int nx = a.nx, ny = a.ny, S = a.S, W = 2 * S + 1;
-  const int mh = nx / 2 + 1, half = nx / 2;
-  const size_t len = (size_t)mh * ny;
+  const int mh = nx / 2 + 1, half = nx / 2, ldy = a.ldy;
+  const size_t len = (size_t)mh * ldy;
   const int lane = threadIdx.x & 63, li = lane & 15, lg = lane >> 4;
-  const int wave = blockIdx.x * kWaves + (threadIdx.x >> 6);
-  const int nwaves = gridDim.x * kWaves;
+  const int wave = blockIdx.x * WAVES + (threadIdx.x >> 6);
+  const int nwaves = gridDim.x * WAVES;
   const int nslots = a.cand ? a.k : a.nq;
-  const int tile_items = kTileImages * kTileSlots;
+  const int ncg = sa.ncg;
+  const int tile_items = kTileImages * kTileSlots * ncg;
   const int n_items = sa.n_ti * sa.n_ts * tile_items;
   const double n = (double)nx * ny, h = 0.5 * n;
   const float c2 = (float)(h - 1.0);
+  const float c2l2e = c2 * 1.4426950408889634f;
+  const bool series = c2 >= 1024.0f;
   const bool fr = li < 8;   // Fr (cos) column of a stage-1 tile; else Fi (sin)
+  // epilogue constants: X = E - O on cosine lanes, E + O on sine lanes
+  const float sgn = fr ? -1.0f : 1.0f;
+  const bool ct_last_ok = (li & 7) <= S - 8 * (NT - 1);
+  const bool ct0_ok = fr || (li & 7) != 0;
+  const int lg4 = 4 * lg, wlast = W - 16 * (NT - 1);
+  // -(n/2-1) log2(e) times the series of log1p: u - u^2/2 + u^3/3 - u^4/4 + u^5/5
+  const float p1 = -c2l2e, p2 = 0.5f * c2l2e, p3 = -c2l2e / 3.0f, p4 = 0.25f * c2l2e, p5 = -0.2f * c2l2e;
 
   for (int item = wave; item < n_items; item += nwaves) {
     const int tile = item / tile_items, rr = item - tile * tile_items;
     const int ti = tile / sa.n_ts, ts = tile - ti * sa.n_ts;
-    const int i = ti * kTileImages + rr / kTileSlots;
-    const int slot = ts * kTileSlots + rr % kTileSlots;
+    const int cg = rr % ncg, pr = rr / ncg;
+    const int i = ti * kTileImages + pr / kTileSlots;
+    const int slot = ts * kTileSlots + pr % kTileSlots;
     if (i >= a.ni || slot >= nslots) continue;   // uniform across the wave
     const int q = a.cand ? a.cand[(size_t)i * a.k + slot] : slot;
     const float2* O = a.ispec + (size_t)i * len;
     const float2* Pq = a.pspec + (size_t)q * len;
     const double A = a.istats[3 * i + 2];
     const int esc = 2 * (a.iexpo[i] + a.pexpo[q]);
-    const double kn = lgamma(h - 1.0) - log(2.0) - 0.5 * log(n) + (1.0 - h) * log(M_PI * A);
+    const int c0 = cg * EW;
+    bioem_erec* out = a.rec + ((size_t)i * nslots + slot) * a.nc;
 
-    double lm = -INFINITY, ls = 0.0, bestv = -INFINITY;
-    int bestc = -1, bestd = -1;
-
-    for (int cg = 0; cg < a.nc && A > 0.0; cg += EW) {
+    if (!(A > 0.0)) {   // degenerate image: every evaluation is void
+      if (lane < EW && c0 + lane < a.nc) out[c0 + lane] = bioem_erec{-1.0f, 0.0f, -1, 0};
+    } else {
       f4 acc2[EW][NT][NT];
 #pragma unroll
       for (int e = 0; e < EW; ++e)
@@ -195,77 +152,107 @@ __global__ __launch_bounds__(kThreads, 1) void k_logpost_split(SplitArgs sa) {
           for (int x = 0; x < NT; ++x) acc1[e][x][0] = acc1[e][x][1] = f4{0.f, 0.f, 0.f, 0.f};
         const int s = 16 * mt + li;          // stage-1 row: spectrum slot
         const bool live = s < half;
-        const bool packed = s == 0;          // slot 0 carries columns 0 and nx/2
-        const float2* Oc = O + (size_t)(live ? s : 0) * ny;
-        const float2* Pc = Pq + (size_t)(live ? s : 0) * ny;
-        for (int ks = 0; ks < KS; ++ks) {
+        const int col = live ? s : 0;
+        const float2* Oc = O + (size_t)col * ldy;
+        const float2* Pc = Pq + (size_t)col * ldy;
+        const float* Tc[EW];
+#pragma unroll
+        for (int e = 0; e < EW; ++e) Tc[e] = a.table + (size_t)min(c0 + e, a.nc - 1) * len + (size_t)col * ldy;
+        const bool pk = mt == 0;             // slot 0 of this tile carries columns 0 and nx/2
+        auto body = [&](const Step<EW>& cur, int ks) {
           const int l0 = 32 * ks + 8 * lg;
-          float2 w0[8], wn[8];
-          {
-            float2 o[8], p[8];
-            load8(Oc, l0, ny, o);
-            load8(Pc, l0, ny, p);
+          float2 w0[8];
+#pragma unroll
+          for (int r = 0; r < 8; ++r) {
+            const float2 o = cur.o[r], p = cur.p[r];
+            w0[r] = live ? make_float2(o.x * p.x + o.y * p.y, o.x * p.y - o.y * p.x) : make_float2(0.f, 0.f);
+          }
+          float zr[EW][8], zi[EW][8];
+#pragma unroll
+          for (int e = 0; e < EW; ++e)
 #pragma unroll
             for (int r = 0; r < 8; ++r) {
-              const float re = o[r].x * p[r].x + o[r].y * p[r].y;
-              const float im = o[r].x * p[r].y - o[r].y * p[r].x;
-              w0[r] = live ? make_float2(re, im) : make_float2(0.f, 0.f);
+              zr[e][r] = w0[r].x * cur.t[e][r];
+              zi[e][r] = w0[r].y * cur.t[e][r];
             }
-            if (packed && l0 == 0) w0[0] = make_float2(0.f, 0.f);   // Z(0,0) := 0
-          }
-          if (packed) {
-            float2 o[8], p[8];
-            load8(O + (size_t)half * ny, l0, ny, o);
-            load8(Pq + (size_t)half * ny, l0, ny, p);
+          if (pk) {
+            if (li == 0) {
+              if (l0 == 0) {   // Z(0,0) := 0
 #pragma unroll
-            for (int r = 0; r < 8; ++r)
-              wn[r] = make_float2(o[r].x * p[r].x + o[r].y * p[r].y, o[r].x * p[r].y - o[r].y * p[r].x);
+                for (int e = 0; e < EW; ++e) zr[e][0] = zi[e][0] = 0.f;
+              }
+              float2 o[8], p[8];
+              load8c(O + (size_t)half * ldy, l0, o);
+              load8c(Pq + (size_t)half * ldy, l0, p);
+#pragma unroll
+              for (int e = 0; e < EW; ++e) {
+                float t[8];
+                load8r(a.table + (size_t)min(c0 + e, a.nc - 1) * len + (size_t)half * ldy, l0, t);
+#pragma unroll
+                for (int r = 0; r < 8; ++r) {
+                  const float wr = o[r].x * p[r].x + o[r].y * p[r].y;
+                  const float wi = o[r].x * p[r].y - o[r].y * p[r].x;
+                  // Z0 + i Zn
+                  zr[e][r] -= wi * t[r];
+                  zi[e][r] += wr * t[r];
+                }
+              }
+            }
+          }
+          V zrh[EW], zrl[EW], zih[EW], zil[EW];
+#pragma unroll
+          for (int e = 0; e < EW; ++e) {
+            split8<BF>(zr[e], zrh[e], zrl[e]);
+            split8<BF>(zi[e], zih[e], zil[e]);
           }
           V fh[NT], fl[NT];
 #pragma unroll
           for (int ct = 0; ct < NT; ++ct) {
-            const uint4 th = Fs[((ks * NT + ct) * 2 + 0) * 64 + lane];
-            const uint4 tl = Fs[((ks * NT + ct) * 2 + 1) * 64 + lane];
-            fh[ct] = __builtin_bit_cast(V, th);
-            fl[ct] = __builtin_bit_cast(V, tl);
+            fh[ct] = __builtin_bit_cast(V, Fs[((ks * NT + ct) * 2 + 0) * 64 + lane]);
+            fl[ct] = __builtin_bit_cast(V, Fs[((ks * NT + ct) * 2 + 1) * 64 + lane]);
           }
+          // three split products, ordered so that no two consecutive MFMAs
+          // update the same accumulator
 #pragma unroll
-          for (int e = 0; e < EW; ++e) {
-            const int c = cg + e;
-            if (c >= a.nc) break;
-            const float2* vc = sa.v + (size_t)c * ny;
-            const float2 u0 = sa.u[(size_t)c * mh + (live ? s : 0)];
-            float zr[8], zi[8];
-            float2 vv[8];
-            load8(vc, l0, ny, vv);
-#pragma unroll
-            for (int r = 0; r < 8; ++r) {
-              const float t = u0.x * vv[r].x - u0.y * vv[r].y;
-              zr[r] = w0[r].x * t;
-              zi[r] = w0[r].y * t;
-            }
-            if (packed) {
-              const float2 un = sa.u[(size_t)c * mh + half];
-#pragma unroll
-              for (int r = 0; r < 8; ++r) {
-                const float t = un.x * vv[r].x - un.y * vv[r].y;
-                // Z0 + i Zn
-                zr[r] -= wn[r].y * t;
-                zi[r] += wn[r].x * t;
-              }
-            }
-            V zrh, zrl, zih, zil;
-            split8<BF>(zr, zrh, zrl);
-            split8<BF>(zi, zih, zil);
+          for (int e = 0; e < EW; ++e)
 #pragma unroll
             for (int ct = 0; ct < NT; ++ct) {
-              acc1[e][ct][0] = P::mma(zrh, fh[ct], acc1[e][ct][0]);
-              acc1[e][ct][0] = P::mma(zrh, fl[ct], acc1[e][ct][0]);
-              acc1[e][ct][0] = P::mma(zrl, fh[ct], acc1[e][ct][0]);
-              acc1[e][ct][1] = P::mma(zih, fh[ct], acc1[e][ct][1]);
-              acc1[e][ct][1] = P::mma(zih, fl[ct], acc1[e][ct][1]);
-              acc1[e][ct][1] = P::mma(zil, fh[ct], acc1[e][ct][1]);
+              acc1[e][ct][0] = P::mma(zrh[e], fh[ct], acc1[e][ct][0]);
+              acc1[e][ct][1] = P::mma(zih[e], fh[ct], acc1[e][ct][1]);
             }
+#pragma unroll
+          for (int e = 0; e < EW; ++e)
+#pragma unroll
+            for (int ct = 0; ct < NT; ++ct) {
+              acc1[e][ct][0] = P::mma(zrh[e], fl[ct], acc1[e][ct][0]);
+              acc1[e][ct][1] = P::mma(zih[e], fl[ct], acc1[e][ct][1]);
+            }
+#pragma unroll
+          for (int e = 0; e < EW; ++e)
+#pragma unroll
+            for (int ct = 0; ct < NT; ++ct) {
+              acc1[e][ct][0] = P::mma(zrl[e], fh[ct], acc1[e][ct][0]);
+              acc1[e][ct][1] = P::mma(zil[e], fh[ct], acc1[e][ct][1]);
+            }
+        };
+        if constexpr (PF) {
+          // two register sets in ping-pong: the loads of the next K-step are
+          // in flight while this one computes, with no copies between sets
+          Step<EW> sa0, sa1;
+          load_step<EW>(sa0, Oc, Pc, Tc, 8 * lg);
+          for (int ks = 0; ks < KS; ks += 2) {
+            if (ks + 1 < KS) load_step<EW>(sa1, Oc, Pc, Tc, 32 * (ks + 1) + 8 * lg);
+            body(sa0, ks);
+            if (ks + 1 < KS) {
+              if (ks + 2 < KS) load_step<EW>(sa0, Oc, Pc, Tc, 32 * (ks + 2) + 8 * lg);
+              body(sa1, ks + 1);
+            }
+          }
+        } else {
+          for (int ks = 0; ks < KS; ++ks) {
+            Step<EW> st;
+            load_step<EW>(st, Oc, Pc, Tc, 32 * ks + 8 * lg);
+            body(st, ks);
           }
         }
         // stage 2: this m-tile is one K-step of the c2r GEMM
@@ -275,9 +262,9 @@ __global__ __launch_bounds__(kThreads, 1) void k_logpost_split(SplitArgs sa) {
           gh[dt] = __builtin_bit_cast(V, Gs[((mt * NT + dt) * 2 + 0) * 64 + lane]);
           gl[dt] = __builtin_bit_cast(V, Gs[((mt * NT + dt) * 2 + 1) * 64 + lane]);
         }
+        V bh[EW][NT], bl[EW][NT];
 #pragma unroll
-        for (int e = 0; e < EW; ++e) {
-          if (cg + e >= a.nc) break;
+        for (int e = 0; e < EW; ++e)
 #pragma unroll
           for (int ct = 0; ct < NT; ++ct) {
             float b[8];
@@ -287,28 +274,43 @@ __global__ __launch_bounds__(kThreads, 1) void k_logpost_split(SplitArgs sa) {
               b[r] = fr ? re : im;
               b[4 + r] = fr ? im : -re;
             }
-            V bh, bl;
-            split8<BF>(b, bh, bl);
-#pragma unroll
-            for (int dt = 0; dt < NT; ++dt) {
-              acc2[e][dt][ct] = P::mma(gh[dt], bh, acc2[e][dt][ct]);
-              acc2[e][dt][ct] = P::mma(gh[dt], bl, acc2[e][dt][ct]);
-              acc2[e][dt][ct] = P::mma(gl[dt], bh, acc2[e][dt][ct]);
-            }
+            split8<BF>(b, bh[e][ct], bl[e][ct]);
           }
-        }
+#pragma unroll
+        for (int e = 0; e < EW; ++e)
+#pragma unroll
+          for (int ct = 0; ct < NT; ++ct)
+#pragma unroll
+            for (int dt = 0; dt < NT; ++dt) acc2[e][dt][ct] = P::mma(gh[dt], bh[e][ct], acc2[e][dt][ct]);
+#pragma unroll
+        for (int e = 0; e < EW; ++e)
+#pragma unroll
+          for (int ct = 0; ct < NT; ++ct)
+#pragma unroll
+            for (int dt = 0; dt < NT; ++dt) acc2[e][dt][ct] = P::mma(gh[dt], bl[e][ct], acc2[e][dt][ct]);
+#pragma unroll
+        for (int e = 0; e < EW; ++e)
+#pragma unroll
+          for (int ct = 0; ct < NT; ++ct)
+#pragma unroll
+            for (int dt = 0; dt < NT; ++dt) acc2[e][dt][ct] = P::mma(gl[dt], bh[e][ct], acc2[e][dt][ct]);
       }
 
-      // likelihood epilogue per CTF set of the group
+      // shift-window epilogue per CTF set of the group (FP32; the FP64
+      // likelihood terms are added at finalisation)
 #pragma unroll
       for (int e = 0; e < EW; ++e) {
-        const int c = cg + e;
-        if (c >= a.nc) break;
+        const int c = c0 + e;
+        if (c >= a.nc) continue;   // uniform
         const double B = a.B[(size_t)q * a.nc + c];
-        if (!(B > 0.0)) continue;
-        float x2v[NT * NT * 4];
-        float x2max = -1.0f;
-        int dbest = 0x7fffffff;
+        if (!(B > 0.0)) {
+          if (lane == 0) out[c] = bioem_erec{-1.0f, 0.0f, -1, 0};
+          continue;
+        }
+        // Pass 1: X = E -+ O from the partner lane, squared in place; only
+        // the last column tile (dy' > S), the dy' = 0 sine column and the
+        // last dx tile (dx > S) hold slots outside the window.
+        float x2max = 0.0f;
 #pragma unroll
         for (int dt = 0; dt < NT; ++dt)
 #pragma unroll
@@ -316,50 +318,43 @@ __global__ __launch_bounds__(kThreads, 1) void k_logpost_split(SplitArgs sa) {
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
               const float mine = acc2[e][dt][ct][r];
-              const float other = __shfl_xor(mine, 8, 64);
-              const float X = fr ? (mine - other) : (other + mine);
-              const int dyp = 8 * ct + (li & 7);
-              const int dxi = 16 * dt + 4 * lg + r;
-              const bool ok = dyp <= S && (fr || dyp > 0) && dxi < W;
-              const int d = ((fr ? dyp : -dyp) + S) * W + dxi;
-              const float x2 = ok ? X * X : -1.0f;
-              x2v[(dt * NT + ct) * 4 + r] = x2;
-              if (ok && (x2 > x2max || (x2 == x2max && d < dbest))) { x2max = x2; dbest = d; }
+              const float X = fmaf(sgn, lane_xor8(mine), mine);
+              float x2 = X * X;
+              bool ok = true;
+              if (ct == NT - 1) ok = ok && ct_last_ok;
+              if (ct == 0) ok = ok && ct0_ok;
+              if (dt == NT - 1) ok = ok && (lg4 + r < wlast);
+              if (ct == NT - 1 || ct == 0 || dt == NT - 1) x2 = ok ? x2 : -1.0f;
+              acc2[e][dt][ct][r] = x2;
+              x2max = fmaxf(x2max, x2);
             }
         const float wmax = wave_max_f(x2max);
-        const int dmax = wave_min_i(x2max == wmax ? dbest : 0x7fffffff);
-        const double kappa = ldexp(1.0, esc) / (n * n * A * B);
+        const double kappa = ldexp(a.kscale / (A * B), esc);
         const double rho2 = fmin((double)wmax * kappa, 1.0 - 0x1p-52);
-        const double lref = kn - 0.5 * log(B) + (1.0 - h) * log1p(-rho2);
         const float cu = (float)(kappa / (1.0 - rho2));
+        const float base = wmax * cu;
+        // Pass 2: sum of (1 + u)^-(n/2-1) over the window.
         float sum = 0.0f;
+        if (series) {
 #pragma unroll
-        for (int k = 0; k < NT * NT * 4; ++k) {
-          if (x2v[k] >= 0.0f) {
-            const float uu = (wmax - x2v[k]) * cu;
-            sum += __expf(-c2 * log1p_acc(uu));
+          for (int k = 0; k < NT * NT * 4; ++k) {
+            const float x2 = acc2[e][k / (4 * NT)][(k / 4) % NT][k % 4];
+            const float u = __builtin_amdgcn_fmed3f(fmaf(-x2, cu, base), 0.0f, 0.05f);
+            // slots outside the window have u clamped to 0.05: below e^-50
+            sum += __builtin_amdgcn_exp2f(u * (p1 + u * (p2 + u * (p3 + u * (p4 + u * p5)))));
+          }
+        } else {
+#pragma unroll
+          for (int k = 0; k < NT * NT * 4; ++k) {
+            const float x2 = acc2[e][k / (4 * NT)][(k / 4) % NT][k % 4];
+            const float u = fmaxf(fmaf(-x2, cu, base), 0.0f);
+            const float t = __expf(-c2 * log1p_acc(u));
+            sum += x2 >= 0.0f ? t : 0.0f;
           }
         }
-        const double tot = wave_sum_d((double)sum);
-        const double le = lref + log(tot);
-        if (le > lm) {
-          ls = ls * exp(lm - le) + 1.0;
-          lm = le;
-        } else {
-          ls += exp(le - lm);
-        }
-        if (lref > bestv) { bestv = lref; bestc = c; bestd = dmax; }
+        const float tot = wave_sum_f(sum);
+        if (lane == 0) out[c] = bioem_erec{wmax, tot, -1, 0};
       }
-    }
-    if (lane == 0) {
-      bioem_rec rec;
-      rec.lse = lm == -INFINITY ? -INFINITY : lm + log(ls);
-      rec.bestl = bestv;
-      rec.q = q;
-      rec.c = bestc;
-      rec.d = bestd;
-      rec.pad = 0;
-      a.rec[(size_t)i * nslots + slot] = rec;
     }
   }
 }
@@ -368,12 +363,11 @@ __global__ __launch_bounds__(kThreads, 1) void k_logpost_split(SplitArgs sa) {
 template <bool BF>
 __global__ void k_split_tables(int nx, int ny, int S, int NT, int KS, int MT, uint4* __restrict__ F,
                                uint4* __restrict__ G) {
-  using E = typename Prec<BF>::E;
   const int nF = KS * NT * 2 * 64, nG = MT * NT * 2 * 64;
   const int idx = blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= nF + nG) return;
   const int W = 2 * S + 1, half = nx / 2;
-  double val[8];
+  float val[8];
   int hl, lane;
   if (idx < nF) {
     lane = idx & 63;
@@ -390,7 +384,7 @@ __global__ void k_split_tables(int nx, int ny, int S, int NT, int KS, int MT, ui
         const double2 t = twiddle64(((long)l * dyp) % ny, ny);
         x = fr ? t.x : t.y;
       }
-      val[r] = x;
+      val[r] = (float)x;
     }
   } else {
     const int k = idx - nF;
@@ -413,45 +407,13 @@ __global__ void k_split_tables(int nx, int ny, int S, int NT, int KS, int MT, ui
           x = re ? 2.0 * w.x : -2.0 * w.y;
         }
       }
-      val[r] = x;
+      val[r] = (float)x;
     }
   }
-  union { uint4 u; E e[8]; } pack;
-  for (int r = 0; r < 8; ++r) {
-    const E hi = (E)(float)val[r];
-    pack.e[r] = hl == 0 ? hi : (E)(float)(val[r] - (double)(float)hi);
-  }
-  (idx < nF ? F[idx] : G[idx - nF]) = pack.u;
-}
-
-// Separable CTF factors: CTF(s) Env(s) = Re(u_m v_l) with
-// u_m = kappa e^{i phi_m} env_m, v_l = e^{i phi_l} env_l, kappa = -A + i sqrt(1-A^2),
-// phi = a s^2 / 2 split into its x and y parts, env = exp(-b s^2/2) likewise.
-__global__ void k_ctf_factors(const double* __restrict__ ctf, int nc, int nx, int ny, double pixel,
-                              float2* __restrict__ u, float2* __restrict__ v) {
-  const int mh = nx / 2 + 1;
-  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= nc * (mh + ny)) return;
-  const int c = idx / (mh + ny), k = idx - c * (mh + ny);
-  const double a = ctf[3 * c], amp = ctf[3 * c + 1], b = ctf[3 * c + 2];
-  if (k < mh) {
-    const double f = 2.0 * M_PI * k / (nx * pixel);
-    const double s2 = f * f;
-    double sn, cs;
-    sincos(0.5 * a * s2, &sn, &cs);
-    const double env = exp(-0.5 * b * s2);
-    const double kr = -amp, ki = sqrt(1.0 - amp * amp);
-    u[(size_t)c * mh + k] = make_float2((float)((kr * cs - ki * sn) * env), (float)((kr * sn + ki * cs) * env));
-  } else {
-    const int l = k - mh;
-    const int ls = (l <= ny / 2) ? l : l - ny;
-    const double f = 2.0 * M_PI * ls / (ny * pixel);
-    const double s2 = f * f;
-    double sn, cs;
-    sincos(0.5 * a * s2, &sn, &cs);
-    const double env = exp(-0.5 * b * s2);
-    v[(size_t)c * ny + l] = make_float2((float)(cs * env), (float)(sn * env));
-  }
+  uint32_t hi[4], lo[4];
+  for (int r = 0; r < 4; ++r) Prec<BF>::split2(val[2 * r], val[2 * r + 1], hi[r], lo[r]);
+  const uint4 out = hl == 0 ? make_uint4(hi[0], hi[1], hi[2], hi[3]) : make_uint4(lo[0], lo[1], lo[2], lo[3]);
+  (idx < nF ? F[idx] : G[idx - nF]) = out;
 }
 
 int nt_for(int S) { return (S + 8) / 8; }   // ceil((S+1)/8) column tiles == ceil((2S+1)/16) dx tiles
@@ -462,15 +424,38 @@ size_t split_smem(int nx, int ny, int S) {
   return (size_t)(KS + MT) * NT * 2 * 64 * sizeof(uint4);
 }
 
-template <bool BF, int NT>
-hipError_t launch_nt(hipStream_t s, const SplitArgs& sa, size_t smem, int grid) {
-  constexpr int EW = 2;
-  auto kern = k_logpost_split<BF, NT, EW>;
+// Launch shapes of the split kernel: CTF sets per wave item, waves per
+// workgroup (4 = one wave per SIMD with up to 512 registers, 8 = two per SIMD
+// with up to 256) and register prefetch of the next K-step.
+struct Shape {
+  int ew, waves;
+  bool pf;
+};
+constexpr Shape kShapes[] = {{2, 4, true}, {2, 8, false}, {1, 8, false}, {4, 4, false}, {2, 4, false}};
+constexpr int kNumShapes = sizeof(kShapes) / sizeof(kShapes[0]);
+
+template <bool BF, int NT, int EW, int WAVES, bool PF>
+hipError_t launch_shape(hipStream_t s, const SplitArgs& sa, size_t smem, int ncu) {
+  auto kern = k_logpost_split<BF, NT, EW, WAVES, PF>;
   hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(kern, dim3(grid), dim3(kThreads), smem, s, sa);
+  const long n_items = (long)sa.n_ti * sa.n_ts * kTileImages * kTileSlots * sa.ncg;
+  const long want = (n_items + WAVES - 1) / WAVES;
+  const int grid = (int)std::min<long>(want, (long)ncu);
+  hipLaunchKernelGGL(kern, dim3(grid), dim3(64 * WAVES), smem, s, sa);
   return hipGetLastError();
+}
+
+template <bool BF, int NT>
+hipError_t launch_nt(hipStream_t s, const SplitArgs& sa, size_t smem, int ncu, int shape) {
+  switch (shape) {
+    case 0: return launch_shape<BF, NT, 2, 4, true>(s, sa, smem, ncu);
+    case 1: return launch_shape<BF, NT, 2, 8, false>(s, sa, smem, ncu);
+    case 2: return launch_shape<BF, NT, 1, 8, false>(s, sa, smem, ncu);
+    case 3: return launch_shape<BF, NT, 4, 4, false>(s, sa, smem, ncu);
+    default: return launch_shape<BF, NT, 2, 4, false>(s, sa, smem, ncu);
+  }
 }
 
 }  // namespace
@@ -480,17 +465,18 @@ bool split_supported(int nx, int ny, int S) {
   return NT >= 1 && NT <= 3 && split_smem(nx, ny, S) <= kMaxSmem;
 }
 
-hipError_t launch_logpost_split(hipStream_t s, const LogpostArgs& a, bool bf16) {
+int split_num_shapes() { return kNumShapes; }
+
+static int split_ctf_groups(int nc, int shape) { return (nc + kShapes[shape].ew - 1) / kShapes[shape].ew; }
+
+hipError_t launch_logpost_split(hipStream_t s, const LogpostArgs& a, bool bf16, int shape) {
+  if (shape < 0 || shape >= kNumShapes) return hipErrorInvalidValue;
   const int NT = nt_for(a.S);
   const int KS = (a.ny + 31) / 32, MT = (a.nx / 2 + 15) / 16;
   const int nF = KS * NT * 2 * 64, nG = MT * NT * 2 * 64;
-  const int mh = a.nx / 2 + 1;
   uint4* tabs = nullptr;
-  float2* fac = nullptr;
   hipError_t e = hipMallocAsync(reinterpret_cast<void**>(&tabs), sizeof(uint4) * (nF + nG), s);
   if (e != hipSuccess) return e;
-  e = hipMallocAsync(reinterpret_cast<void**>(&fac), sizeof(float2) * (size_t)a.nc * (mh + a.ny), s);
-  if (e != hipSuccess) { hipFreeAsync(tabs, s); return e; }
   const int nt = nF + nG;
   if (bf16)
     hipLaunchKernelGGL(k_split_tables<true>, dim3((nt + 255) / 256), dim3(256), 0, s, a.nx, a.ny, a.S, NT, KS, MT,
@@ -498,35 +484,27 @@ hipError_t launch_logpost_split(hipStream_t s, const LogpostArgs& a, bool bf16) 
   else
     hipLaunchKernelGGL(k_split_tables<false>, dim3((nt + 255) / 256), dim3(256), 0, s, a.nx, a.ny, a.S, NT, KS, MT,
                        tabs, tabs + nF);
-  const int nfac = a.nc * (mh + a.ny);
-  hipLaunchKernelGGL(k_ctf_factors, dim3((nfac + 255) / 256), dim3(256), 0, s, a.ctf, a.nc, a.nx, a.ny,
-                     a.pixel, fac, fac + (size_t)a.nc * mh);
   SplitArgs sa;
   sa.a = a;
   sa.F = tabs;
   sa.G = tabs + nF;
-  sa.u = fac;
-  sa.v = fac + (size_t)a.nc * mh;
   sa.KS = KS;
   sa.MT = MT;
+  sa.ncg = split_ctf_groups(a.nc, shape);
   const int nslots = a.cand ? a.k : a.nq;
   sa.n_ti = (a.ni + kTileImages - 1) / kTileImages;
   sa.n_ts = (nslots + kTileSlots - 1) / kTileSlots;
-  const long n_items = (long)sa.n_ti * sa.n_ts * kTileImages * kTileSlots;
   int dev = 0, ncu = 256;
   if (hipGetDevice(&dev) == hipSuccess) {
     int v = 0;
     if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && v > 0) ncu = v;
   }
-  const long want = (n_items + kWaves - 1) / kWaves;
-  const int grid = (int)std::min<long>(want, (long)ncu);
   const size_t smem = split_smem(a.nx, a.ny, a.S);
-  if (NT == 1) e = bf16 ? launch_nt<true, 1>(s, sa, smem, grid) : launch_nt<false, 1>(s, sa, smem, grid);
-  else if (NT == 2) e = bf16 ? launch_nt<true, 2>(s, sa, smem, grid) : launch_nt<false, 2>(s, sa, smem, grid);
-  else e = bf16 ? launch_nt<true, 3>(s, sa, smem, grid) : launch_nt<false, 3>(s, sa, smem, grid);
-  hipFreeAsync(fac, s);
-  hipFreeAsync(tabs, s);
-  return e;
+  if (NT == 1) e = bf16 ? launch_nt<true, 1>(s, sa, smem, ncu, shape) : launch_nt<false, 1>(s, sa, smem, ncu, shape);
+  else if (NT == 2) e = bf16 ? launch_nt<true, 2>(s, sa, smem, ncu, shape) : launch_nt<false, 2>(s, sa, smem, ncu, shape);
+  else e = bf16 ? launch_nt<true, 3>(s, sa, smem, ncu, shape) : launch_nt<false, 3>(s, sa, smem, ncu, shape);
+  const hipError_t f = hipFreeAsync(tabs, s);
+  return e != hipSuccess ? e : f;
 }
 
 }  // namespace bioem

@@ -141,11 +141,14 @@ __global__ __launch_bounds__(128) void k_cdft_cols(const double2* __restrict__ r
 }
 
 // Scale each item's spectrum by 2^-e with e the exponent of its largest
-// magnitude (so all |values| < 1) and store as FP32.  grid: n; block: 256.
-__global__ __launch_bounds__(256) void k_spec_store(const double2* __restrict__ spec64, int len,
-                                                    float2* __restrict__ spec, int32_t* __restrict__ expo) {
+// magnitude (so all |values| < 1) and store as FP32 with each column padded
+// with zeros to ldy rows.  grid: n; block: 256.
+__global__ __launch_bounds__(256) void k_spec_store(const double2* __restrict__ spec64, int mh, int ny,
+                                                    int ldy, float2* __restrict__ spec,
+                                                    int32_t* __restrict__ expo) {
   __shared__ double red[256];
   const size_t item = blockIdx.x;
+  const int len = mh * ny;
   const double2* src = spec64 + item * len;
   double mx = 0.0;
   for (int e = threadIdx.x; e < len; e += 256) mx = fmax(mx, fmax(fabs(src[e].x), fabs(src[e].y)));
@@ -158,9 +161,16 @@ __global__ __launch_bounds__(256) void k_spec_store(const double2* __restrict__ 
   int ex = 0;
   if (red[0] > 0.0) frexp(red[0], &ex);
   if (threadIdx.x == 0) expo[item] = ex;
-  float2* dst = spec + item * len;
-  for (int e = threadIdx.x; e < len; e += 256)
-    dst[e] = make_float2((float)ldexp(src[e].x, -ex), (float)ldexp(src[e].y, -ex));
+  float2* dst = spec + item * (size_t)mh * ldy;
+  for (int e = threadIdx.x; e < mh * ldy; e += 256) {
+    const int m = e / ldy, l = e - m * ldy;
+    float2 v = make_float2(0.f, 0.f);
+    if (l < ny) {
+      const double2 x = src[m * ny + l];
+      v = make_float2((float)ldexp(x.x, -ex), (float)ldexp(x.y, -ex));
+    }
+    dst[e] = v;
+  }
 }
 
 // Deterministic FP64 block sum over 256 threads.
@@ -226,7 +236,7 @@ __global__ __launch_bounds__(256) void k_render_filter(const float2* __restrict_
   if (e >= len) return;
   const int m = e / ny, l = e - m * ny;
   const double t = ctf_env(ctf[3 * item], ctf[3 * item + 1], ctf[3 * item + 2], m, l, nx, ny, pixel);
-  const float2 v = spec[item * len + e];
+  const float2 v = spec[item * (size_t)mh * spec_ld(ny) + (size_t)m * spec_ld(ny) + l];
   const double sc = ldexp(1.0, expo[item]) * t;
   out[item * len + e] = make_double2(v.x * sc, v.y * sc);
 }
@@ -316,12 +326,13 @@ __global__ __launch_bounds__(256) void k_render_finish(const double* __restrict_
 
 __global__ __launch_bounds__(256) void k_ctf_table(const double* __restrict__ ctf, int nx, int ny,
                                                    double pixel, float* __restrict__ table) {
-  const int mh = nx / 2 + 1, len = mh * ny;
+  const int mh = nx / 2 + 1, ldy = spec_ld(ny), len = mh * ldy;
   const int c = blockIdx.y;
   const int e = blockIdx.x * 256 + threadIdx.x;
   if (e >= len) return;
-  const int m = e / ny, l = e - m * ny;
-  table[(size_t)c * len + e] = (float)ctf_env(ctf[3 * c], ctf[3 * c + 1], ctf[3 * c + 2], m, l, nx, ny, pixel);
+  const int m = e / ldy, l = e - m * ldy;
+  table[(size_t)c * len + e] =
+      l < ny ? (float)ctf_env(ctf[3 * c], ctf[3 * c + 1], ctf[3 * c + 2], m, l, nx, ny, pixel) : 0.0f;
 }
 
 // B_qc = (1/n) sum_{s != 0} w_s |P_q(s) T_c(s)|^2 (Plancherel), FP64.
@@ -331,14 +342,14 @@ __global__ __launch_bounds__(256) void k_proj_norms(const float2* __restrict__ p
                                                     const float* __restrict__ table, int nc, int nx,
                                                     int ny, double* __restrict__ B) {
   __shared__ double red[256];
-  const int mh = nx / 2 + 1, len = mh * ny;
+  const int mh = nx / 2 + 1, ldy = spec_ld(ny), len = mh * ldy;
   const int q = blockIdx.x / nc, c = blockIdx.x - q * nc;
   const float2* p = pspec + (size_t)q * len;
   const float* t = table + (size_t)c * len;
   double acc = 0.0;
   for (int e = threadIdx.x; e < len; e += 256) {
-    if (e == 0) continue;
-    const int m = e / ny;
+    if (e == 0) continue;   // the DC term is excluded (the mean is integrated out)
+    const int m = e / ldy;
     const double w = (m == 0 || 2 * m == nx) ? 1.0 : 2.0;
     const double tt = t[e];
     const double re = p[e].x * tt, im = p[e].y * tt;
@@ -369,7 +380,7 @@ hipError_t launch_rdft2(hipStream_t s, const double* real_in, const float* real_
 
 hipError_t launch_spec_store(hipStream_t s, const double2* spec64, int n, int nx, int ny,
                              float2* spec, int32_t* expo) {
-  hipLaunchKernelGGL(k_spec_store, dim3(n), dim3(256), 0, s, spec64, (nx / 2 + 1) * ny, spec, expo);
+  hipLaunchKernelGGL(k_spec_store, dim3(n), dim3(256), 0, s, spec64, nx / 2 + 1, ny, spec_ld(ny), spec, expo);
   return last();
 }
 
@@ -394,7 +405,7 @@ hipError_t launch_render(hipStream_t s, const float2* spec, const int32_t* expo,
 
 hipError_t launch_ctf_table(hipStream_t s, const double* ctf, int nc, int nx, int ny, double pixel,
                             float* table) {
-  const int len = (nx / 2 + 1) * ny;
+  const int len = (nx / 2 + 1) * spec_ld(ny);
   hipLaunchKernelGGL(k_ctf_table, dim3((len + 255) / 256, nc), dim3(256), 0, s, ctf, nx, ny, pixel, table);
   return last();
 }
