@@ -99,7 +99,7 @@ int split_shape_for(bioem_ctx* ctx, int nx, int ny, int S, int nc) {
     const int v = std::atoi(env);
     if (v >= 0 && v < split_num_shapes()) return v;
   }
-  return 0;
+  return 3;
 }
 
 int chunk_items(int n, size_t per_item) {
