@@ -26,10 +26,23 @@ if ROOT not in sys.path:
 
 METRIC = "posterior evals/s (image×orient×CTF, all shifts) @224² px; |Δlog P| vs FP64"
 
-# Algorithmic work per evaluation at 224^2, S = 20 (pointwise product, pruned
-# inverse transform counted as an FFT, likelihood epilogue): FP32 and FP64 flops.
-ALG_FP32_PER_EVAL = 6 * 224 * 113 + 113 * 5 * 224 * math.log2(224) + 41 * 2.5 * 224 * math.log2(224)
-ALG_FP64_PER_EVAL = 1681 * 45
+
+
+def alg_flops(n: int, S: int):
+    """Algorithmic work of one evaluation (image x orientation x CTF set, all
+    (2S+1)^2 shifts) on an n x n box: FP32 flops of the pointwise product
+    (6 per half-spectrum coefficient) and of the pruned inverse transform
+    counted as FFTs (stage 1: n/2+1 complex columns of 5 n log2 n; stage 2:
+    2S+1 real rows of 2.5 n log2 n), and FP64 flops of the likelihood and
+    log-sum-exp (45 per shift)."""
+    h = n * (n // 2 + 1)
+    lg = math.log2(n)
+    fp32 = 6 * h + (n // 2 + 1) * 5 * n * lg + (2 * S + 1) * 2.5 * n * lg
+    fp64 = (2 * S + 1) ** 2 * 45
+    return fp32, fp64
+
+
+ALG_FP32_PER_EVAL, ALG_FP64_PER_EVAL = alg_flops(224, 20)
 PEAK_FP32_TFLOPS = 157.3
 PEAK_FP64_TFLOPS = 78.6
 
@@ -115,6 +128,9 @@ def main() -> int:
     ap.add_argument("--images", type=int, default=1000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", default="2x8x2")
+    ap.add_argument("--workload", default="paper224", choices=["paper224", "mixed"],
+                    help="paper224: 224^2, 1000 images x 4608 orientations x 8 CTF sets (default); "
+                         "mixed: 96/128/180/224 px classes x two models in one persistent launch")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB three times (the reference "
                          "kernel for scaling HBM traffic counters) and exit")
@@ -143,6 +159,8 @@ def main() -> int:
         return 0
     P.load()
     ctx = P.Context(0)
+    if args.workload == "mixed":
+        return run_mixed(args, P, ctx, torch, dev)
 
     # ---- inputs, resident in HBM ------------------------------------------------
     log("generating the 224^2 workload")
@@ -219,6 +237,107 @@ def main() -> int:
     if not args.no_cpu_baseline:
         log(f"timing the CPU oracle on a {args.cpu_sample} sample")
         line["cpu_baseline"] = cpu_baseline(args.cpu_sample)
+    print(json.dumps(line), flush=True)
+    ctx.close()
+    return 0
+
+
+def run_mixed(args, P, ctx, torch, dev) -> int:
+    """Four box sizes x two models scored in one persistent launch, against
+    one launch per job.  A step is bioem_project of every (class, model) grid,
+    bioem_prepare_images of every class and the posterior of every image
+    under both models."""
+    import numpy as np
+    from workloads import make_workload
+    per = args.images if args.images != 1000 else 2500
+    log(f"generating the mixed-size workload ({per} images per class)")
+    wl = make_workload(4, n_images=per)
+    models = [torch.from_numpy(m).to(dev) for m in wl.models]
+    classes = []
+    evals = 0
+    fp_equiv = 0.0
+    for cls in wl.classes:
+        imgs = torch.empty((per, cls.ny, cls.nx), dtype=torch.float32, device=dev)
+        for m in range(2):
+            idx = np.nonzero(cls.img_model == m)[0]
+            if len(idx) == 0:
+                continue
+            pr = P.project(ctx, models[m], torch.from_numpy(cls.img_quat[idx]).to(dev), cls.nx, cls.ny,
+                           cls.pixel_A)
+            noise = np.concatenate([cls.noise(int(i), int(i) + 1) for i in idx])
+            imgs[torch.from_numpy(idx).to(dev)] = P.render(
+                ctx, pr, torch.from_numpy(cls.img_ctf[idx]).to(dev),
+                torch.from_numpy(cls.img_shift[idx]).to(dev), noise=torch.from_numpy(noise).to(dev),
+                snr=cls.snr, device_out=True)
+            pr.free()
+        classes.append(dict(cls=cls, imgs=imgs, quats=torch.from_numpy(cls.quats).to(dev),
+                            ctf=torch.from_numpy(cls.ctf).to(dev)))
+        e = 2 * per * len(cls.quats) * len(cls.ctf)
+        evals += e
+        f32, f64 = alg_flops(cls.nx, cls.max_shift)
+        fp_equiv += e * (f32 + 2.0 * f64)
+    torch.cuda.synchronize()
+    log(f"inputs ready: {evals} evaluations per step")
+
+    def step(mode):
+        handles, jobs = [], []
+        for c in classes:
+            cls = c["cls"]
+            im = P.prepare_images(ctx, c["imgs"])
+            handles.append(im)
+            for m in range(2):
+                pr = P.project(ctx, models[m], c["quats"], cls.nx, cls.ny, cls.pixel_A)
+                handles.append(pr)
+                jobs.append(dict(proj=pr, imgs=im, ctf=c["ctf"], max_shift=cls.max_shift))
+        outs = P.logpost_batch(ctx, jobs, prec=args.prec, mode=mode, device_out=True)
+        for h in handles:
+            h.free()
+        return outs
+
+    ctx.set_autotune(True)
+    res = {}
+    for mode in ("persistent", "per_job"):
+        for w in range(args.warmup):
+            step(mode)
+            torch.cuda.synchronize()
+            log(f"{mode}: warmup {w + 1}/{args.warmup} done")
+        ctx.set_timing(True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for k in range(args.steps):
+            outs = step(mode)
+            torch.cuda.synchronize()
+            log(f"{mode}: step {k + 1}/{args.steps} done")
+        dt = (time.perf_counter() - t0) / args.steps
+        kms, launches, kevals = ctx.kernel_time()
+        ctx.set_timing(False)
+        for o in outs:
+            assert bool(torch.isfinite(o["logp"]).all()), "non-finite log posterior"
+        res[mode] = dict(dt=dt, kms=kms / args.steps, launches=launches // args.steps)
+        log(f"{mode}: {evals / dt:.4g} evals/s, kernel {kms / args.steps:.1f} ms per step")
+    p, q = res["persistent"], res["per_job"]
+    achieved = fp_equiv / (p["kms"] * 1e-3) / 1e12
+    line = {"metric": METRIC, "value": evals / p["dt"], "unit": "evals/s", "n_gpus": 1,
+            "steps": args.steps, "warmup": args.warmup, "ms_per_step": p["dt"] * 1e3,
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+            "dtype": {"f32": "f32 transform, f64 likelihood",
+                      "split_f16": "f16x2 split on MFMA (f32 acc), f64 likelihood",
+                      "split_bf16": "bf16x2 split on MFMA (f32 acc), f64 likelihood"}[args.prec],
+            "data": "synthetic",
+            "config": {"workload": f"mixed sizes: 96/128/180/224 px x {per} images each, two models "
+                                   "(1000 and 2500 spheres), grids (1152,4) (2304,8) (3456,12) "
+                                   "(4608,16), shifts 8/11/16/20, one persistent launch",
+                       "evals_per_step": evals, "prec": args.prec,
+                       "step": "bioem_project + bioem_prepare_images + bioem_logpost_batch"},
+            "roofline": {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP32_TFLOPS,
+                         "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_TFLOPS, 4),
+                         "traffic": None, "kernel": "k_logpost_batch",
+                         "kernel_ms_per_launch": round(p["kms"] / max(p["launches"], 1), 3),
+                         "launches": p["launches"]},
+            "per_job": {"value": evals / q["dt"], "ms_per_step": q["dt"] * 1e3,
+                        "kernel_ms_per_step": q["kms"], "launches_per_step": q["launches"]},
+            "persistent_over_per_job": q["dt"] / p["dt"],
+            "tuning": ctx.tunings()}
     print(json.dumps(line), flush=True)
     ctx.close()
     return 0

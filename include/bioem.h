@@ -150,6 +150,127 @@ bioem_status bioem_logpost(bioem_ctx* ctx, const bioem_proj* proj, const bioem_i
                            const double* ctf, int32_t nc, bioem_mem ctf_mem, int32_t max_shift,
                            const bioem_opts* opts, double* logp, bioem_best* best);
 
+/* One job of a batched call: a projection set and an image set of the same
+ * box, their CTF grid and shift window, an optional proposal, and outputs.
+ * Field meanings are those of bioem_logpost's arguments and options. */
+typedef struct {
+  const bioem_proj* proj;
+  const bioem_imgs* imgs;
+  const double* ctf;       /* [nc][3], host or device per ctf_mem */
+  int32_t nc;
+  int32_t ctf_mem;
+  int32_t max_shift;
+  int32_t k;               /* candidates per image (with cand_q) */
+  const int32_t* cand_q;   /* [ni][k] or NULL for the full grid */
+  int32_t cand_mem;
+  int32_t reserved;        /* must be zero */
+  double* logp;            /* [ni] or NULL */
+  bioem_best* best;        /* [ni] or NULL */
+  double* logp_orient;     /* [ni][nq] or NULL */
+} bioem_job;
+
+/* Batch modes. */
+typedef enum {
+  BIOEM_BATCH_PERSISTENT = 0,  /* every job's evaluations in one persistent launch */
+  BIOEM_BATCH_PER_JOB = 1      /* one launch per job, in order (for comparison) */
+} bioem_batch_mode;
+
+/* Score several jobs (different boxes, shift windows, grids, models) with
+ * results identical in meaning to one bioem_logpost per job.  With a split
+ * precision and BIOEM_BATCH_PERSISTENT the per-evaluation work of all jobs
+ * runs in ONE persistent kernel launch whose workgroups sweep the jobs'
+ * concatenated work lists (each workgroup gets a near-equal share of every
+ * job, so boxes of different cost balance); per-job CTF tables, norms and
+ * the FP64 finalisation run as separate small launches.  With
+ * BIOEM_PREC_F32 jobs run one after another whatever the mode.  prec and
+ * out_mem apply to every job.  Every job is validated before any work is
+ * enqueued; the job list is borrowed for the call. */
+bioem_status bioem_logpost_batch(bioem_ctx* ctx, const bioem_job* jobs, int32_t njobs, int32_t prec,
+                                 int32_t out_mem, int32_t mode);
+
+/* Autotuning of the split-precision kernel's tile shape (CTF sets per wave
+ * item, item tile of images x orientations).  While enabled, the first
+ * bioem_logpost / bioem_logpost_batch call that meets a new key
+ * (nx, ny, S, orientation-count bucket floor(log2 nq), precision) times every
+ * candidate shape on a sample of that call's own work (up to 32 images x 512
+ * orientations) and keeps the fastest for the context's lifetime; later calls
+ * with the key use it.  Disabled (the default): a fixed default shape.
+ * Results do not depend on the shape beyond floating-point summation order. */
+bioem_status bioem_set_autotune(bioem_ctx* ctx, int32_t enable);
+
+/* A tuned entry: its key, the chosen shape and the sampled timings. */
+typedef struct {
+  int32_t nx, ny, max_shift, nq_log2, prec;
+  int32_t ew;              /* CTF sets per wave item */
+  int32_t tile_images;     /* item tile */
+  int32_t tile_slots;
+  double ns_per_eval;      /* chosen shape on the sample */
+  double ns_per_eval_default;  /* default shape on the sample */
+} bioem_tuning;
+
+/* Number of tuned entries of ctx, and entry idx in [0, count). */
+int32_t bioem_tuning_count(const bioem_ctx* ctx);
+bioem_status bioem_tuning_entry(const bioem_ctx* ctx, int32_t idx, bioem_tuning* out);
+
+/* ---- learned orientation proposal ------------------------------------------
+ * A small BF16 convolutional network maps a particle image to logits over
+ * the orientation grid; its top-K orientations per image are the candidate
+ * list of bioem_logpost (opts.cand_q).  It is trained on the per-orientation
+ * posteriors the method itself computes (Section 3, Extra features), by the
+ * forward and backward kernels of this library (bf16 matrix-core products
+ * with FP32 accumulation, FP32 master weights, Adam).
+ *
+ * Architecture (sizes from bioem_cnn_arch): per-image standardisation; four
+ * 3x3 convolutions with stride 2 and zero padding 1 (1 -> c1 -> c2 -> c3 ->
+ * c4 channels, ReLU); spatial mean; a hidden layer of `hidden` units (ReLU);
+ * a linear layer to nq logits.  Loss: mean soft-label cross entropy against
+ * sparse targets (idx, p) per image.  Parameters are one flat FP32 vector:
+ * W1 [c1][1][3][3], b1 [c1], W2 [c2][c1][3][3], b2, W3, b3, W4, b4,
+ * F1 [hidden][c4], g1 [hidden], F2 [nq][hidden], g2 [nq].
+ * Images are [B][box][box] float32; box must be a multiple of 16 (16..512). */
+typedef struct bioem_cnn bioem_cnn;
+
+typedef struct {
+  int32_t box, c1, c2, c3, c4, hidden, nq;
+  int32_t reserved;        /* must be zero */
+} bioem_cnn_arch;
+
+/* Create a network on ctx's device with zero parameters; the caller sets
+ * them (bioem_cnn_set_params).  Release with bioem_cnn_destroy. */
+bioem_status bioem_cnn_create(bioem_ctx* ctx, const bioem_cnn_arch* arch, bioem_cnn** out);
+void bioem_cnn_destroy(bioem_cnn* net);
+int64_t bioem_cnn_num_params(const bioem_cnn* net);
+/* Copy all parameters in / out (flat order above); setting them also resets
+ * the optimiser state.  mem: bioem_mem of params. */
+bioem_status bioem_cnn_set_params(bioem_ctx* ctx, bioem_cnn* net, const float* params, int32_t mem);
+bioem_status bioem_cnn_get_params(bioem_ctx* ctx, const bioem_cnn* net, float* params, int32_t mem);
+/* Logits [B][nq] of B images (internally in batches of up to 256). */
+bioem_status bioem_cnn_forward(bioem_ctx* ctx, bioem_cnn* net, const float* imgs, int32_t B, int32_t in_mem,
+                               float* logits, int32_t out_mem);
+/* Loss and gradient of one batch (B <= 256): targets tidx [B][T] int32 and
+ * tp [B][T] float32 (each row sums to 1), memory per in_mem like imgs.  The
+ * gradient is kept in the network for bioem_cnn_adam and also copied to
+ * grad [nparams] when grad is not NULL (per grad_mem).  *loss (host) is the
+ * batch mean. */
+bioem_status bioem_cnn_backward(bioem_ctx* ctx, bioem_cnn* net, const float* imgs, int32_t B,
+                                const int32_t* tidx, const float* tp, int32_t T, int32_t in_mem, float* loss,
+                                float* grad, int32_t grad_mem);
+/* One Adam step (bias-corrected) with the last gradient. */
+bioem_status bioem_cnn_adam(bioem_ctx* ctx, bioem_cnn* net, float lr, float beta1, float beta2, float eps);
+/* Top-K orientations per image (K <= nq), in increasing index order, ties to
+ * the lower index: cand [B][K] int32, and the softmax mass they hold
+ * mass [B] float32 (NULL to skip); outputs per out_mem. */
+bioem_status bioem_cnn_propose(bioem_ctx* ctx, bioem_cnn* net, const float* imgs, int32_t B, int32_t in_mem,
+                               int32_t K, int32_t* cand, float* mass, int32_t out_mem);
+
+/* Top-K of each row of z [B][n] float32 (host or device per in_mem): idx
+ * [B][K] int32 in increasing index order (ties to the lower index) and the
+ * softmax mass of the selection, mass [B] (NULL to skip), per out_mem.  With
+ * z a per-orientation log posterior this is the posterior mass the K most
+ * probable orientations hold (the proposal's training targets). */
+bioem_status bioem_topk(bioem_ctx* ctx, const float* z, int32_t B, int32_t n, int32_t K, int32_t in_mem,
+                        int32_t* idx, float* mass, int32_t out_mem);
+
 /* Synthetic maps (Section 3, Extra features): one calculated image per
  * projection, I_cal(r) = N I1(r + d) - mu + sigma eps with
  * I1 = F^-1[F(I0) CTF Env] and sigma^2 = var(I1)/snr.

@@ -18,6 +18,10 @@ special values).  The absolute level of log P depends on the prior reading
 (flat N and mu, Jeffreys lambda, uniform normalised grid priors); the paper
 prints no posterior values, so that level is "parity unpinned" beyond the
 closed-form integral itself.
+
+``cnn_oracle`` is the FP64 reference of the orientation-proposal network
+(forward, backward, cross entropy, top-K), pinned by finite differences and a
+library correlation; it is likewise test infrastructure only.
 """
 from .bioem_oracle import (  # noqa: F401
     quat_to_matrix, project_model, ctf_envelope_table, filtered_projection,

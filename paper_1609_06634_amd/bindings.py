@@ -47,6 +47,29 @@ class Opts(ctypes.Structure):
                 ("logp_orient", ctypes.c_void_p), ("reserved", ctypes.c_int32 * 4)]
 
 
+class Job(ctypes.Structure):
+    _fields_ = [("proj", ctypes.c_void_p), ("imgs", ctypes.c_void_p), ("ctf", ctypes.c_void_p),
+                ("nc", ctypes.c_int32), ("ctf_mem", ctypes.c_int32), ("max_shift", ctypes.c_int32),
+                ("k", ctypes.c_int32), ("cand_q", ctypes.c_void_p), ("cand_mem", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("logp", ctypes.c_void_p), ("best", ctypes.c_void_p),
+                ("logp_orient", ctypes.c_void_p)]
+
+
+class Tuning(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("max_shift", ctypes.c_int32),
+                ("nq_log2", ctypes.c_int32), ("prec", ctypes.c_int32), ("ew", ctypes.c_int32),
+                ("tile_images", ctypes.c_int32), ("tile_slots", ctypes.c_int32),
+                ("ns_per_eval", ctypes.c_double), ("ns_per_eval_default", ctypes.c_double)]
+
+
+class CnnArch(ctypes.Structure):
+    _fields_ = [("box", ctypes.c_int32), ("c1", ctypes.c_int32), ("c2", ctypes.c_int32),
+                ("c3", ctypes.c_int32), ("c4", ctypes.c_int32), ("hidden", ctypes.c_int32),
+                ("nq", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+BATCH_PERSISTENT, BATCH_PER_JOB = 0, 1
+
 _lib = None
 
 # (name, restype, argtypes) of every exported entry point.
@@ -69,6 +92,20 @@ SIGNATURES = [
     ("bioem_ctf_from_physical", _I, [_D, _D, _D, _D, ctypes.POINTER(_D)]),
     ("bioem_set_timing", _I, [_P, _I]),
     ("bioem_get_kernel_time", _I, [_P, ctypes.POINTER(_D), ctypes.POINTER(_I), ctypes.POINTER(_D)]),
+    ("bioem_logpost_batch", _I, [_P, ctypes.POINTER(Job), _I, _I, _I, _I]),
+    ("bioem_set_autotune", _I, [_P, _I]),
+    ("bioem_tuning_count", _I, [_P]),
+    ("bioem_tuning_entry", _I, [_P, _I, ctypes.POINTER(Tuning)]),
+    ("bioem_cnn_create", _I, [_P, ctypes.POINTER(CnnArch), ctypes.POINTER(_P)]),
+    ("bioem_cnn_destroy", None, [_P]),
+    ("bioem_cnn_num_params", ctypes.c_int64, [_P]),
+    ("bioem_cnn_set_params", _I, [_P, _P, _P, _I]),
+    ("bioem_cnn_get_params", _I, [_P, _P, _P, _I]),
+    ("bioem_cnn_forward", _I, [_P, _P, _P, _I, _I, _P, _I]),
+    ("bioem_cnn_backward", _I, [_P, _P, _P, _I, _P, _P, _I, _I, ctypes.POINTER(ctypes.c_float), _P, _I]),
+    ("bioem_cnn_adam", _I, [_P, _P, ctypes.c_float, ctypes.c_float, ctypes.c_float, ctypes.c_float]),
+    ("bioem_cnn_propose", _I, [_P, _P, _P, _I, _I, _I, _P, _P, _I]),
+    ("bioem_topk", _I, [_P, _P, _I, _I, _I, _I, _P, _P, _I]),
 ]
 
 
@@ -78,6 +115,12 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     if _lib is None:
         if not os.path.exists(path):
             raise ImportError(f"{path} not built: run paper_1609_06634_amd.build.build()")
+        # torch ships its own HIP runtime; loading it first makes the library
+        # bind to that same runtime (one runtime per process, shared streams)
+        try:
+            import torch  # noqa: F401
+        except ImportError:  # pragma: no cover - torch is a dependency
+            pass
         lib = ctypes.CDLL(path)
         for name, res, args in SIGNATURES:
             fn = getattr(lib, name)
@@ -148,6 +191,18 @@ class Context:
         self.check(self._lib.bioem_get_kernel_time(self.h, ctypes.byref(ms), ctypes.byref(n),
                                                    ctypes.byref(ev)))
         return ms.value, n.value, ev.value
+
+    def set_autotune(self, enable: bool = True):
+        self.check(self._lib.bioem_set_autotune(self.h, 1 if enable else 0))
+
+    def tunings(self):
+        """Tuned entries of this context as a list of dicts."""
+        out = []
+        for i in range(self._lib.bioem_tuning_count(self.h)):
+            t = Tuning()
+            self.check(self._lib.bioem_tuning_entry(self.h, i, ctypes.byref(t)))
+            out.append({f: getattr(t, f) for f, _ in Tuning._fields_})
+        return out
 
     def close(self):
         if getattr(self, "h", None):
@@ -240,6 +295,138 @@ def logpost(ctx: Context, proj: Projections, imgs: Images, ctf, max_shift: int,
     ctx.check(ctx._lib.bioem_logpost(ctx.h, proj.h, imgs.h, cp, nc, cm, max_shift, ctypes.byref(o),
                                      logp.ctypes.data, best.ctypes.data))
     return {"logp": logp, "best": best, "orient": orient_a}
+
+
+def logpost_batch(ctx: Context, jobs, prec: str = "split_f16", mode: str = "persistent",
+                  orient: bool = False, device_out: bool = False):
+    """Score several jobs in one call.  ``jobs`` is a list of dicts with keys
+    proj, imgs, ctf, max_shift and optionally cand_q.  Returns one dict per
+    job, as ``logpost`` does."""
+    arr = (Job * len(jobs))()
+    keep, outs = [], []
+    torch = _torch() if device_out else None
+    for j, jb in enumerate(jobs):
+        proj, imgs = jb["proj"], jb["imgs"]
+        cp, cm, ck = _arg(jb["ctf"], np.float64)
+        keep.append(ck)
+        J = arr[j]
+        J.proj, J.imgs, J.ctf, J.nc, J.ctf_mem, J.max_shift = proj.h, imgs.h, cp, int(ck.shape[0]), cm, \
+            int(jb["max_shift"])
+        if jb.get("cand_q") is not None:
+            qp, qm, qk = _arg(jb["cand_q"], np.int32)
+            J.cand_q, J.k, J.cand_mem = qp, int(qk.shape[1]), qm
+            keep.append(qk)
+        ni, nq = imgs.n, proj.n
+        if device_out:
+            dev = torch.device("cuda", ctx.device)
+            o = {"logp": torch.empty(ni, dtype=torch.float64, device=dev),
+                 "best": torch.empty(ni * ctypes.sizeof(Best), dtype=torch.uint8, device=dev),
+                 "orient": torch.empty((ni, nq), dtype=torch.float64, device=dev) if orient else None}
+            J.logp, J.best = o["logp"].data_ptr(), o["best"].data_ptr()
+            J.logp_orient = o["orient"].data_ptr() if orient else None
+        else:
+            o = {"logp": np.empty(ni, np.float64), "best": np.empty(ni, BEST_DTYPE),
+                 "orient": np.empty((ni, nq), np.float64) if orient else None}
+            J.logp, J.best = o["logp"].ctypes.data, o["best"].ctypes.data
+            J.logp_orient = o["orient"].ctypes.data if orient else None
+        outs.append(o)
+    m = {"persistent": BATCH_PERSISTENT, "per_job": BATCH_PER_JOB}[mode]
+    ctx.check(ctx._lib.bioem_logpost_batch(ctx.h, arr, len(jobs), PREC[prec],
+                                           MEM_DEVICE if device_out else MEM_HOST, m))
+    return outs
+
+
+def topk(ctx: Context, z, K: int, device_out: bool = False):
+    """(idx [B][K] int32, mass [B] float32) of the K largest entries per row."""
+    zp, m, keep = _arg(z, np.float32)
+    B, n = (int(v) for v in keep.shape)
+    if device_out:
+        torch = _torch()
+        dev = torch.device("cuda", ctx.device)
+        idx = torch.empty((B, K), dtype=torch.int32, device=dev)
+        mass = torch.empty(B, dtype=torch.float32, device=dev)
+        ctx.check(ctx._lib.bioem_topk(ctx.h, zp, B, n, K, m, idx.data_ptr(), mass.data_ptr(), MEM_DEVICE))
+        return idx, mass
+    idx = np.empty((B, K), np.int32)
+    mass = np.empty(B, np.float32)
+    ctx.check(ctx._lib.bioem_topk(ctx.h, zp, B, n, K, m, idx.ctypes.data, mass.ctypes.data, MEM_HOST))
+    return idx, mass
+
+
+class Net:
+    """The orientation-proposal network of a context (see bioem_cnn_* in
+    include/bioem.h).  Arrays are numpy (host) or torch CUDA tensors."""
+
+    def __init__(self, ctx: Context, box: int, c1: int, c2: int, c3: int, c4: int, hidden: int, nq: int):
+        self.ctx = ctx
+        self.arch = CnnArch(box, c1, c2, c3, c4, hidden, nq, 0)
+        h = ctypes.c_void_p()
+        ctx.check(ctx._lib.bioem_cnn_create(ctx.h, ctypes.byref(self.arch), ctypes.byref(h)))
+        self.h = h
+        self.nparams = int(ctx._lib.bioem_cnn_num_params(h))
+        self.box, self.nq = box, nq
+
+    def set_params(self, params):
+        p, m, keep = _arg(params, np.float32, (self.nparams,))
+        self.ctx.check(self.ctx._lib.bioem_cnn_set_params(self.ctx.h, self.h, p, m))
+
+    def get_params(self) -> np.ndarray:
+        out = np.empty(self.nparams, np.float32)
+        self.ctx.check(self.ctx._lib.bioem_cnn_get_params(self.ctx.h, self.h, out.ctypes.data, MEM_HOST))
+        return out
+
+    def forward(self, imgs) -> np.ndarray:
+        ip, m, keep = _arg(imgs, np.float32)
+        B = int(keep.shape[0])
+        out = np.empty((B, self.nq), np.float32)
+        self.ctx.check(self.ctx._lib.bioem_cnn_forward(self.ctx.h, self.h, ip, B, m, out.ctypes.data, MEM_HOST))
+        return out
+
+    def backward(self, imgs, tidx, tp, want_grad: bool = False):
+        """(loss, gradient or None) of one batch; the gradient stays in the
+        network for ``adam``."""
+        ip, m, keep = _arg(imgs, np.float32)
+        B = int(keep.shape[0])
+        qi, m2, k2 = _arg(tidx, np.int32)
+        qp, m3, k3 = _arg(tp, np.float32)
+        if len({m, m2, m3}) != 1:
+            raise ValueError("images and targets must all be host or all device")
+        T = int(k2.shape[1])
+        loss = ctypes.c_float()
+        g = np.empty(self.nparams, np.float32) if want_grad else None
+        self.ctx.check(self.ctx._lib.bioem_cnn_backward(
+            self.ctx.h, self.h, ip, B, qi, qp, T, m, ctypes.byref(loss),
+            g.ctypes.data if want_grad else None, MEM_HOST))
+        return loss.value, g
+
+    def adam(self, lr: float, beta1: float = 0.9, beta2: float = 0.999, eps: float = 1e-8):
+        self.ctx.check(self.ctx._lib.bioem_cnn_adam(self.ctx.h, self.h, lr, beta1, beta2, eps))
+
+    def propose(self, imgs, K: int, device_out: bool = False):
+        """(cand [B][K] int32, mass [B] float32)."""
+        ip, m, keep = _arg(imgs, np.float32)
+        B = int(keep.shape[0])
+        if device_out:
+            torch = _torch()
+            dev = torch.device("cuda", self.ctx.device)
+            cand = torch.empty((B, K), dtype=torch.int32, device=dev)
+            mass = torch.empty(B, dtype=torch.float32, device=dev)
+            self.ctx.check(self.ctx._lib.bioem_cnn_propose(self.ctx.h, self.h, ip, B, m, K, cand.data_ptr(),
+                                                           mass.data_ptr(), MEM_DEVICE))
+            return cand, mass
+        cand = np.empty((B, K), np.int32)
+        mass = np.empty(B, np.float32)
+        self.ctx.check(self.ctx._lib.bioem_cnn_propose(self.ctx.h, self.h, ip, B, m, K, cand.ctypes.data,
+                                                       mass.ctypes.data, MEM_HOST))
+        return cand, mass
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.ctx._lib.bioem_cnn_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        self.close()
 
 
 def best_from_bytes(t) -> np.ndarray:

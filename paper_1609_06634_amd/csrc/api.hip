@@ -9,88 +9,20 @@
 #include <vector>
 
 #include "common.hpp"
+#include "host_util.hpp"
 
 using namespace bioem;
+using namespace bioem::host;
 
 namespace {
 
-constexpr size_t kScratchBudget = size_t(256) << 20;   // per transform chunk
+constexpr size_t kScratchBudget = size_t(1) << 30;     // per transform chunk
 constexpr size_t kRecordBudget = size_t(1) << 30;      // per posterior image chunk
-
-bioem_status fail(bioem_ctx* ctx, bioem_status st, const char* fmt, ...) {
-  if (ctx) {
-    char buf[512];
-    va_list ap;
-    va_start(ap, fmt);
-    vsnprintf(buf, sizeof buf, fmt, ap);
-    va_end(ap);
-    ctx->err = buf;
-  }
-  return st;
-}
-
-#define HIP_OR_FAIL(ctx, expr)                                                              \
-  do {                                                                                      \
-    hipError_t e_ = (expr);                                                                 \
-    if (e_ != hipSuccess)                                                                   \
-      return fail(ctx, e_ == hipErrorOutOfMemory ? BIOEM_ENOMEM : BIOEM_EDEVICE, "%s: %s", \
-                  #expr, hipGetErrorString(e_));                                            \
-  } while (0)
-
-// Device buffer that frees itself.
-struct DevMem {
-  void* p = nullptr;
-  DevMem() = default;
-  DevMem(const DevMem&) = delete;
-  DevMem& operator=(const DevMem&) = delete;
-  ~DevMem() { if (p) (void)hipFree(p); }
-  hipError_t alloc(size_t bytes) { return hipMalloc(&p, bytes ? bytes : 1); }
-  template <class T> T* as() const { return static_cast<T*>(p); }
-};
-
-// A borrowed input made available on the device: used in place when it is
-// device memory, copied (stream-ordered) when it is host memory.
-struct DevIn {
-  DevMem own;
-  const void* d = nullptr;
-  hipError_t set(const void* src, size_t bytes, bioem_mem mem, hipStream_t s) {
-    if (!src) { d = nullptr; return hipSuccess; }
-    if (mem == BIOEM_MEM_DEVICE) { d = src; return hipSuccess; }
-    hipError_t e = own.alloc(bytes);
-    if (e != hipSuccess) return e;
-    d = own.p;
-    return hipMemcpyAsync(own.p, src, bytes, hipMemcpyHostToDevice, s);
-  }
-  template <class T> const T* as() const { return static_cast<const T*>(d); }
-};
-
-// Small inputs are validated on the host; device ones are copied back first.
-template <class T>
-hipError_t to_host(const T* src, size_t count, bioem_mem mem, hipStream_t s, std::vector<T>& out) {
-  out.resize(count);
-  if (count == 0) return hipSuccess;
-  if (mem == BIOEM_MEM_HOST) {
-    std::memcpy(out.data(), src, count * sizeof(T));
-    return hipSuccess;
-  }
-  hipError_t e = hipMemcpyAsync(out.data(), src, count * sizeof(T), hipMemcpyDeviceToHost, s);
-  if (e != hipSuccess) return e;
-  return hipStreamSynchronize(s);
-}
-
-bool finite_all(const double* v, size_t n) {
-  for (size_t i = 0; i < n; ++i)
-    if (!std::isfinite(v[i])) return false;
-  return true;
-}
-
-bool valid_mem(int m) { return m == BIOEM_MEM_HOST || m == BIOEM_MEM_DEVICE; }
 
 bool valid_box(int nx, int ny) {
   return nx >= 4 && ny >= 4 && nx <= kMaxBox && ny <= kMaxBox && nx % 2 == 0 && ny % 2 == 0;
 }
 
-// Items per transform chunk so that the FP64 scratch stays within budget.
 // Launch shape of the split kernel: BIOEM_SPLIT_SHAPE overrides the default.
 int split_shape_for(bioem_ctx* ctx, int nx, int ny, int S, int nc) {
   (void)ctx; (void)nx; (void)ny; (void)S; (void)nc;
@@ -102,10 +34,329 @@ int split_shape_for(bioem_ctx* ctx, int nx, int ny, int S, int nc) {
   return 3;
 }
 
+// Items per transform chunk so that the FP64 scratch stays within budget.
 int chunk_items(int n, size_t per_item) {
   size_t c = kScratchBudget / (per_item ? per_item : 1);
   if (c < 1) c = 1;
   return (int)std::min<size_t>(c, (size_t)n);
+}
+
+}  // namespace
+
+
+// ---- posterior jobs --------------------------------------------------------
+
+namespace {
+
+constexpr size_t kBatchRecordBudget = size_t(16) << 30;   // records of one persistent launch
+
+// A validated bioem_logpost job with its device-side inputs, tables and
+// output staging.
+struct Job {
+  const bioem_proj* proj = nullptr;
+  const bioem_imgs* imgs = nullptr;
+  int nx = 0, ny = 0, nq = 0, ni = 0, nc = 0, S = 0, k = 0, nslots = 0;
+  double log_prior = 0.0;
+  bool has_cand = false;
+  DevIn dctf, dcand;
+  DevMem table, B;
+  DevMem dlogp, dbest, dorient;
+  double* d_logp = nullptr;
+  bioem_best* d_best = nullptr;
+  double* d_orient = nullptr;
+  double* logp = nullptr;          // caller's outputs
+  bioem_best* best = nullptr;
+  double* orient = nullptr;
+  size_t len = 0;                  // stored spectrum stride
+  Job() = default;
+  Job(Job&&) = default;
+};
+
+bioem_status plan_job(bioem_ctx* ctx, const bioem_job& jb, int prec, int out_mem, Job& J, const char* who) {
+  const bioem_proj* proj = jb.proj;
+  const bioem_imgs* imgs = jb.imgs;
+  if (!proj || !imgs || !jb.ctf) return fail(ctx, BIOEM_EINVAL, "%s: NULL handle or ctf", who);
+  if (!valid_mem(jb.ctf_mem) || !valid_mem(out_mem) || (jb.cand_q && !valid_mem(jb.cand_mem)))
+    return fail(ctx, BIOEM_EINVAL, "%s: bad mem kind", who);
+  if (prec != BIOEM_PREC_F32 && prec != BIOEM_PREC_SPLIT_BF16 && prec != BIOEM_PREC_SPLIT_F16)
+    return fail(ctx, BIOEM_EINVAL, "%s: unknown precision mode %d", who, prec);
+  const int nx = proj->nx, ny = proj->ny, nq = proj->n, ni = imgs->n, nc = jb.nc, S = jb.max_shift;
+  if (imgs->nx != nx || imgs->ny != ny)
+    return fail(ctx, BIOEM_EINVAL, "%s: image box %dx%d differs from projection box %dx%d", who, imgs->nx,
+                imgs->ny, nx, ny);
+  if (proj->device != ctx->device || imgs->device != ctx->device)
+    return fail(ctx, BIOEM_EINVAL, "%s: handle on another device", who);
+  if ((long)nx * ny <= 2) return fail(ctx, BIOEM_EINVAL, "%s: need more than 2 pixels", who);
+  if (nc < 1) return fail(ctx, BIOEM_EINVAL, "%s: need nc >= 1 CTF sets", who);
+  if (S < 0 || 2 * S >= std::min(nx, ny))
+    return fail(ctx, BIOEM_EINVAL, "%s: max_shift %d outside [0, min(nx,ny)/2)", who, S);
+  if (jb.cand_q && (jb.k < 1 || jb.k > nq))
+    return fail(ctx, BIOEM_EINVAL, "%s: candidate count k=%d outside [1, %d]", who, jb.k, nq);
+  hipStream_t s = ctx->stream;
+  std::vector<double> hc;
+  HIP_OR_FAIL(ctx, to_host(jb.ctf, (size_t)nc * 3, (bioem_mem)jb.ctf_mem, s, hc));
+  if (!finite_all(hc.data(), hc.size())) return fail(ctx, BIOEM_EINVAL, "%s: non-finite CTF value", who);
+  for (int c = 0; c < nc; ++c)
+    if (!(hc[3 * c + 1] >= 0.0 && hc[3 * c + 1] <= 1.0))
+      return fail(ctx, BIOEM_EINVAL, "%s: amplitude contrast of CTF %d outside [0,1]", who, c);
+  const bool split = prec != BIOEM_PREC_F32;
+  if (split && !split_supported(nx, ny, S))
+    return fail(ctx, BIOEM_EUNSUPPORTED, "%s: split-precision kernel does not support %dx%d with S=%d", who,
+                nx, ny, S);
+  if (!split && f32_smem_bytes(nx, ny, S) > kMaxSmem)
+    return fail(ctx, BIOEM_EUNSUPPORTED, "%s: shift window too large for the F32 kernel", who);
+  std::vector<int32_t> hcand;
+  if (jb.cand_q) {
+    HIP_OR_FAIL(ctx, to_host(jb.cand_q, (size_t)ni * jb.k, (bioem_mem)jb.cand_mem, s, hcand));
+    for (size_t e = 0; e < hcand.size(); ++e)
+      if (hcand[e] < 0 || hcand[e] >= nq)
+        return fail(ctx, BIOEM_EINVAL, "%s: candidate %zu = %d outside [0, %d)", who, e, hcand[e], nq);
+  }
+  J.proj = proj; J.imgs = imgs;
+  J.nx = nx; J.ny = ny; J.nq = nq; J.ni = ni; J.nc = nc; J.S = S;
+  J.has_cand = jb.cand_q != nullptr;
+  J.k = J.has_cand ? jb.k : 0;
+  J.nslots = J.has_cand ? jb.k : nq;
+  const int W = 2 * S + 1;
+  J.log_prior = -std::log((double)nq) - std::log((double)nc) - std::log((double)W * W);
+  J.len = (size_t)(nx / 2 + 1) * spec_ld(ny);
+  HIP_OR_FAIL(ctx, J.dctf.set(hc.data(), hc.size() * 8, BIOEM_MEM_HOST, s));
+  if (J.has_cand) HIP_OR_FAIL(ctx, J.dcand.set(hcand.data(), hcand.size() * 4, BIOEM_MEM_HOST, s));
+  HIP_OR_FAIL(ctx, J.table.alloc(sizeof(float) * J.len * nc));
+  HIP_OR_FAIL(ctx, J.B.alloc(sizeof(double) * (size_t)nq * nc));
+  HIP_OR_FAIL(ctx, launch_ctf_table(s, J.dctf.as<double>(), nc, nx, ny, proj->pixel, J.table.as<float>()));
+  HIP_OR_FAIL(ctx, launch_proj_norms(s, proj->spec, proj->expo, nq, J.table.as<float>(), nc, nx, ny,
+                                     J.B.as<double>()));
+  J.logp = jb.logp; J.best = jb.best; J.orient = jb.logp_orient;
+  J.d_logp = jb.logp; J.d_best = jb.best; J.d_orient = jb.logp_orient;
+  if (out_mem == BIOEM_MEM_HOST) {
+    if (J.logp) { HIP_OR_FAIL(ctx, J.dlogp.alloc(8 * (size_t)ni)); J.d_logp = J.dlogp.as<double>(); }
+    if (J.best) { HIP_OR_FAIL(ctx, J.dbest.alloc(sizeof(bioem_best) * (size_t)ni)); J.d_best = J.dbest.as<bioem_best>(); }
+    if (J.orient) { HIP_OR_FAIL(ctx, J.dorient.alloc(8 * (size_t)ni * nq)); J.d_orient = J.dorient.as<double>(); }
+  }
+  return BIOEM_OK;
+}
+
+// Kernel arguments of images [i0, i0 + cn) of a job, records at rec.
+LogpostArgs job_args(const Job& J, int i0, int cn, bioem_erec* rec) {
+  LogpostArgs a{};
+  a.ispec = J.imgs->spec + J.len * i0; a.iexpo = J.imgs->expo + i0; a.istats = J.imgs->stats + 3 * (size_t)i0;
+  a.ni = cn;
+  a.pspec = J.proj->spec; a.pexpo = J.proj->expo; a.nq = J.nq;
+  a.table = J.table.as<float>(); a.B = J.B.as<double>(); a.nc = J.nc;
+  a.nx = J.nx; a.ny = J.ny; a.S = J.S; a.ldy = spec_ld(J.ny);
+  a.cand = J.has_cand ? J.dcand.as<int32_t>() + (size_t)i0 * J.k : nullptr; a.k = J.k;
+  a.rec = rec;
+  a.kscale = 1.0 / ((double)J.nx * J.ny * (double)J.nx * J.ny);
+  return a;
+}
+
+hipError_t finalize_chunk(hipStream_t s, const Job& J, const LogpostArgs& a, int i0, bool split) {
+  FinalizeArgs f{};
+  f.rec = a.rec; f.ni = a.ni; f.nslots = J.nslots; f.nc = J.nc; f.nq_total = J.nq; f.nx = J.nx; f.ny = J.ny;
+  f.S = J.S; f.cand = a.cand; f.k = J.k;
+  f.istats = a.istats; f.iexpo = a.iexpo; f.pexpo = J.proj->expo; f.B = a.B;
+  f.log_prior = J.log_prior;
+  f.logp = J.d_logp ? J.d_logp + i0 : nullptr;
+  f.best = J.d_best ? J.d_best + i0 : nullptr;
+  f.orient = J.d_orient ? J.d_orient + (size_t)i0 * J.nq : nullptr;
+  hipError_t e = launch_finalize(s, f);
+  if (e == hipSuccess && split && f.best) e = launch_best_shift(s, a, f.best);
+  return e;
+}
+
+bioem_status ensure_events(bioem_ctx* ctx, int n) {
+  while ((int)ctx->ev_start.size() < ctx->ev_used + n) {
+    hipEvent_t a, b;
+    HIP_OR_FAIL(ctx, hipEventCreate(&a));
+    HIP_OR_FAIL(ctx, hipEventCreate(&b));
+    ctx->ev_start.push_back(a);
+    ctx->ev_stop.push_back(b);
+  }
+  return BIOEM_OK;
+}
+
+// Tile shape of the split kernel for a job: the tuned entry of its key, a
+// new tuning run, or the default (BIOEM_SPLIT_SHAPE overrides the variant).
+struct SplitCfg {
+  int shape, ew, ti, ts;
+};
+
+constexpr int kTuneEW[] = {4, 2};
+constexpr int kTuneTiles[][2] = {{16, 128}, {8, 256}, {32, 64}, {4, 512}};
+
+int ilog2(int v) {
+  int r = 0;
+  while (v > 1) { v >>= 1; ++r; }
+  return r;
+}
+
+bioem_status tune_job(bioem_ctx* ctx, const Job& J, int prec, bioem_tuning& out) {
+  hipStream_t s = ctx->stream;
+  const bool bf16 = prec == BIOEM_PREC_SPLIT_BF16;
+  const int ni_s = std::min(J.ni, 32);
+  const int nslots_s = J.has_cand ? J.k : std::min(J.nq, 512);
+  DevMem rec;
+  HIP_OR_FAIL(ctx, rec.alloc(sizeof(bioem_erec) * (size_t)ni_s * nslots_s * J.nc));
+  LogpostArgs a = job_args(J, 0, ni_s, rec.as<bioem_erec>());
+  if (!J.has_cand) a.nq = nslots_s;   // the first orientations stand for the grid
+  hipEvent_t e0, e1;
+  HIP_OR_FAIL(ctx, hipEventCreate(&e0));
+  HIP_OR_FAIL(ctx, hipEventCreate(&e1));
+  const double evals = (double)ni_s * nslots_s * J.nc;
+  double best = 1e300, def = 1e300;
+  int bew = 4, bti = kTuneTiles[0][0], bts = kTuneTiles[0][1];
+  hipError_t err = hipSuccess;
+  for (int ew : kTuneEW)
+    for (const auto& t : kTuneTiles) {
+      const int shape = split_shape_for_ew(ew);
+      float ms = 0.0f;
+      for (int rep = 0; rep < 2 && err == hipSuccess; ++rep) {   // first run warms the caches
+        err = hipEventRecord(e0, s);
+        if (err == hipSuccess) err = launch_logpost_split(s, a, bf16, shape, t[0], t[1]);
+        if (err == hipSuccess) err = hipEventRecord(e1, s);
+        if (err == hipSuccess) err = hipEventSynchronize(e1);
+        if (err == hipSuccess) err = hipEventElapsedTime(&ms, e0, e1);
+      }
+      if (err != hipSuccess) break;
+      const double ns = ms * 1e6 / evals;
+      if (ew == 4 && t[0] == kTuneTiles[0][0] && t[1] == kTuneTiles[0][1]) def = ns;
+      if (ns < best) { best = ns; bew = ew; bti = t[0]; bts = t[1]; }
+    }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (err != hipSuccess) return fail(ctx, BIOEM_EDEVICE, "autotune: %s", hipGetErrorString(err));
+  out = bioem_tuning{};
+  out.nx = J.nx; out.ny = J.ny; out.max_shift = J.S; out.nq_log2 = ilog2(J.nq); out.prec = prec;
+  out.ew = bew; out.tile_images = bti; out.tile_slots = bts;
+  out.ns_per_eval = best; out.ns_per_eval_default = def;
+  return BIOEM_OK;
+}
+
+bioem_status split_cfg(bioem_ctx* ctx, const Job& J, int prec, SplitCfg& cfg) {
+  cfg = SplitCfg{split_shape_for(ctx, J.nx, J.ny, J.S, J.nc), 4, 0, 0};
+  if (std::getenv("BIOEM_SPLIT_SHAPE") || !ctx->autotune) {
+    cfg.ew = cfg.shape == split_shape_for_ew(2) ? 2 : 4;
+    return BIOEM_OK;
+  }
+  const int lq = ilog2(J.nq);
+  for (const bioem_tuning& t : ctx->tuned)
+    if (t.nx == J.nx && t.ny == J.ny && t.max_shift == J.S && t.nq_log2 == lq && t.prec == prec) {
+      cfg = SplitCfg{split_shape_for_ew(t.ew), t.ew, t.tile_images, t.tile_slots};
+      return BIOEM_OK;
+    }
+  bioem_tuning t;
+  const bioem_status st = tune_job(ctx, J, prec, t);
+  if (st != BIOEM_OK) return st;
+  ctx->tuned.push_back(t);
+  cfg = SplitCfg{split_shape_for_ew(t.ew), t.ew, t.tile_images, t.tile_slots};
+  return BIOEM_OK;
+}
+
+// One job: image chunks bounded by the record budget, main kernel, then the
+// FP64 finalisation of each chunk.
+bioem_status run_job(bioem_ctx* ctx, Job& J, int prec) {
+  hipStream_t s = ctx->stream;
+  const bool split = prec != BIOEM_PREC_F32;
+  SplitCfg cfg{0, 4, 0, 0};
+  if (split) {
+    const bioem_status st = split_cfg(ctx, J, prec, cfg);
+    if (st != BIOEM_OK) return st;
+  }
+  const size_t per_image = sizeof(bioem_erec) * (size_t)J.nslots * J.nc;
+  const int chunk = (int)std::max<size_t>(1, std::min<size_t>(J.ni, kRecordBudget / per_image));
+  DevMem rec;
+  HIP_OR_FAIL(ctx, rec.alloc(per_image * chunk));
+  const int nchunks = (J.ni + chunk - 1) / chunk;
+  if (ctx->timing) {
+    const bioem_status st = ensure_events(ctx, nchunks);
+    if (st != BIOEM_OK) return st;
+  }
+  for (int i0 = 0; i0 < J.ni; i0 += chunk) {
+    const int cn = std::min(chunk, J.ni - i0);
+    const LogpostArgs a = job_args(J, i0, cn, rec.as<bioem_erec>());
+    if (ctx->timing) HIP_OR_FAIL(ctx, hipEventRecord(ctx->ev_start[ctx->ev_used], s));
+    hipError_t e = split ? launch_logpost_split(s, a, prec == BIOEM_PREC_SPLIT_BF16, cfg.shape, cfg.ti, cfg.ts)
+                         : launch_logpost_f32(s, a);
+    if (ctx->timing && e == hipSuccess) {
+      HIP_OR_FAIL(ctx, hipEventRecord(ctx->ev_stop[ctx->ev_used], s));
+      ++ctx->ev_used;
+      ctx->timed_evals += (double)cn * J.nslots * J.nc;
+    }
+    if (e == hipSuccess) e = finalize_chunk(s, J, a, i0, split);
+    if (e != hipSuccess) return fail(ctx, BIOEM_EDEVICE, "bioem_logpost: launch failed: %s", hipGetErrorString(e));
+  }
+  return BIOEM_OK;
+}
+
+// Every job's evaluations in one persistent launch (per round of image
+// chunks when the records of all jobs exceed the budget), then per-job
+// finalisation.
+bioem_status run_batch_persistent(bioem_ctx* ctx, std::vector<Job>& J, int prec) {
+  hipStream_t s = ctx->stream;
+  const int nj = (int)J.size();
+  std::vector<SplitCfg> cfg(nj);
+  size_t total = 0;
+  for (int j = 0; j < nj; ++j) {
+    const bioem_status st = split_cfg(ctx, J[j], prec, cfg[j]);
+    if (st != BIOEM_OK) return st;
+    total += sizeof(bioem_erec) * (size_t)J[j].ni * J[j].nslots * J[j].nc;
+  }
+  const int rounds = (int)std::max<size_t>(1, (total + kBatchRecordBudget - 1) / kBatchRecordBudget);
+  std::vector<int> chunk(nj);
+  size_t per_round = 0;
+  for (int j = 0; j < nj; ++j) {
+    chunk[j] = std::max(1, (J[j].ni + rounds - 1) / rounds);
+    per_round += sizeof(bioem_erec) * (size_t)chunk[j] * J[j].nslots * J[j].nc;
+  }
+  DevMem rec;
+  HIP_OR_FAIL(ctx, rec.alloc(per_round));
+  if (ctx->timing) {
+    const bioem_status st = ensure_events(ctx, rounds);
+    if (st != BIOEM_OK) return st;
+  }
+  for (int r = 0; r < rounds; ++r) {
+    std::vector<BatchJob> bj;
+    std::vector<int> which, first;
+    size_t off = 0;
+    double evals = 0.0;
+    for (int j = 0; j < nj; ++j) {
+      const int i0 = r * chunk[j];
+      if (i0 >= J[j].ni) continue;
+      const int cn = std::min(chunk[j], J[j].ni - i0);
+      BatchJob b;
+      b.a = job_args(J[j], i0, cn, reinterpret_cast<bioem_erec*>(static_cast<char*>(rec.p) + off));
+      b.ew = cfg[j].ew; b.ti = cfg[j].ti; b.ts = cfg[j].ts;
+      bj.push_back(b);
+      which.push_back(j);
+      first.push_back(i0);
+      off += sizeof(bioem_erec) * (size_t)cn * J[j].nslots * J[j].nc;
+      evals += (double)cn * J[j].nslots * J[j].nc;
+    }
+    if (bj.empty()) continue;
+    if (ctx->timing) HIP_OR_FAIL(ctx, hipEventRecord(ctx->ev_start[ctx->ev_used], s));
+    hipError_t e = launch_logpost_batch(s, bj.data(), (int)bj.size(), prec == BIOEM_PREC_SPLIT_BF16);
+    if (ctx->timing && e == hipSuccess) {
+      HIP_OR_FAIL(ctx, hipEventRecord(ctx->ev_stop[ctx->ev_used], s));
+      ++ctx->ev_used;
+      ctx->timed_evals += evals;
+    }
+    for (size_t b = 0; b < bj.size() && e == hipSuccess; ++b) e = finalize_chunk(s, J[which[b]], bj[b].a, first[b], true);
+    if (e != hipSuccess)
+      return fail(ctx, BIOEM_EDEVICE, "bioem_logpost_batch: launch failed: %s", hipGetErrorString(e));
+  }
+  return BIOEM_OK;
+}
+
+bioem_status copy_out(bioem_ctx* ctx, Job& J, int out_mem) {
+  if (out_mem != BIOEM_MEM_HOST) return BIOEM_OK;
+  hipStream_t s = ctx->stream;
+  if (J.logp) HIP_OR_FAIL(ctx, hipMemcpyAsync(J.logp, J.d_logp, 8 * (size_t)J.ni, hipMemcpyDeviceToHost, s));
+  if (J.best)
+    HIP_OR_FAIL(ctx, hipMemcpyAsync(J.best, J.d_best, sizeof(bioem_best) * (size_t)J.ni, hipMemcpyDeviceToHost, s));
+  if (J.orient)
+    HIP_OR_FAIL(ctx, hipMemcpyAsync(J.orient, J.d_orient, 8 * (size_t)J.ni * J.nq, hipMemcpyDeviceToHost, s));
+  return BIOEM_OK;
 }
 
 }  // namespace
@@ -395,125 +646,65 @@ bioem_status bioem_logpost(bioem_ctx* ctx, const bioem_proj* proj, const bioem_i
                            const double* ctf, int32_t nc, bioem_mem ctf_mem, int32_t max_shift,
                            const bioem_opts* opts, double* logp, bioem_best* best) {
   if (!ctx) return BIOEM_EINVAL;
-  if (!proj || !imgs || !ctf) return fail(ctx, BIOEM_EINVAL, "bioem_logpost: NULL handle or ctf");
   bioem_opts o{};
   if (opts) o = *opts;
   if (o.reserved[0] || o.reserved[1] || o.reserved[2] || o.reserved[3])
     return fail(ctx, BIOEM_EINVAL, "bioem_logpost: opts.reserved must be zero");
-  if (!valid_mem(ctf_mem) || !valid_mem(o.out_mem) || (o.cand_q && !valid_mem(o.cand_mem)))
-    return fail(ctx, BIOEM_EINVAL, "bioem_logpost: bad mem kind");
-  if (o.prec != BIOEM_PREC_F32 && o.prec != BIOEM_PREC_SPLIT_BF16 && o.prec != BIOEM_PREC_SPLIT_F16)
-    return fail(ctx, BIOEM_EINVAL, "bioem_logpost: unknown precision mode %d", o.prec);
-  const int nx = proj->nx, ny = proj->ny, nq = proj->n, ni = imgs->n;
-  if (imgs->nx != nx || imgs->ny != ny)
-    return fail(ctx, BIOEM_EINVAL, "bioem_logpost: image box %dx%d differs from projection box %dx%d",
-                imgs->nx, imgs->ny, nx, ny);
-  if ((long)nx * ny <= 2) return fail(ctx, BIOEM_EINVAL, "bioem_logpost: need more than 2 pixels");
-  if (nc < 1) return fail(ctx, BIOEM_EINVAL, "bioem_logpost: need nc >= 1 CTF sets");
-  if (max_shift < 0 || 2 * max_shift >= std::min(nx, ny))
-    return fail(ctx, BIOEM_EINVAL, "bioem_logpost: max_shift %d outside [0, min(nx,ny)/2)", max_shift);
-  if (o.cand_q && (o.k < 1 || o.k > nq))
-    return fail(ctx, BIOEM_EINVAL, "bioem_logpost: candidate count k=%d outside [1, %d]", o.k, nq);
+  bioem_job jb{};
+  jb.proj = proj; jb.imgs = imgs; jb.ctf = ctf; jb.nc = nc; jb.ctf_mem = ctf_mem; jb.max_shift = max_shift;
+  jb.k = o.k; jb.cand_q = o.cand_q; jb.cand_mem = o.cand_mem;
+  jb.logp = logp; jb.best = best; jb.logp_orient = o.logp_orient;
   HIP_OR_FAIL(ctx, hipSetDevice(ctx->device));
-  hipStream_t s = ctx->stream;
-  std::vector<double> hc;
-  HIP_OR_FAIL(ctx, to_host(ctf, (size_t)nc * 3, ctf_mem, s, hc));
-  if (!finite_all(hc.data(), hc.size())) return fail(ctx, BIOEM_EINVAL, "bioem_logpost: non-finite CTF value");
-  for (int c = 0; c < nc; ++c)
-    if (!(hc[3 * c + 1] >= 0.0 && hc[3 * c + 1] <= 1.0))
-      return fail(ctx, BIOEM_EINVAL, "bioem_logpost: amplitude contrast of CTF %d outside [0,1]", c);
-  const bool split = o.prec != BIOEM_PREC_F32;
-  if (split && !split_supported(nx, ny, max_shift))
-    return fail(ctx, BIOEM_EUNSUPPORTED, "bioem_logpost: split-precision kernel does not support %dx%d with S=%d",
-                nx, ny, max_shift);
-  if (!split && f32_smem_bytes(nx, ny, max_shift) > kMaxSmem)
-    return fail(ctx, BIOEM_EUNSUPPORTED, "bioem_logpost: shift window too large for the F32 kernel");
-  std::vector<int32_t> hcand;
-  if (o.cand_q) {
-    HIP_OR_FAIL(ctx, to_host(o.cand_q, (size_t)ni * o.k, (bioem_mem)o.cand_mem, s, hcand));
-    for (size_t e = 0; e < hcand.size(); ++e)
-      if (hcand[e] < 0 || hcand[e] >= nq)
-        return fail(ctx, BIOEM_EINVAL, "bioem_logpost: candidate %zu = %d outside [0, %d)", e, hcand[e], nq);
-  }
-  const int mh = nx / 2 + 1;
-  const size_t len = (size_t)mh * spec_ld(ny);   // stored spectrum / table stride
-  DevIn dctf, dcand;
-  HIP_OR_FAIL(ctx, dctf.set(hc.data(), hc.size() * 8, BIOEM_MEM_HOST, s));
-  if (o.cand_q) HIP_OR_FAIL(ctx, dcand.set(hcand.data(), hcand.size() * 4, BIOEM_MEM_HOST, s));
-  DevMem table, B;
-  HIP_OR_FAIL(ctx, table.alloc(sizeof(float) * len * nc));
-  HIP_OR_FAIL(ctx, B.alloc(sizeof(double) * (size_t)nq * nc));
-  HIP_OR_FAIL(ctx, launch_ctf_table(s, dctf.as<double>(), nc, nx, ny, proj->pixel, table.as<float>()));
-  HIP_OR_FAIL(ctx, launch_proj_norms(s, proj->spec, proj->expo, nq, table.as<float>(), nc, nx, ny, B.as<double>()));
-
-  // outputs (device staging when the caller wants host memory)
-  const bool host_out = o.out_mem == BIOEM_MEM_HOST;
-  DevMem dlogp, dbest, dorient;
-  double* d_logp = logp;
-  bioem_best* d_best = best;
-  double* d_orient = o.logp_orient;
-  if (host_out) {
-    if (logp) { HIP_OR_FAIL(ctx, dlogp.alloc(8 * (size_t)ni)); d_logp = dlogp.as<double>(); }
-    if (best) { HIP_OR_FAIL(ctx, dbest.alloc(sizeof(bioem_best) * (size_t)ni)); d_best = dbest.as<bioem_best>(); }
-    if (o.logp_orient) { HIP_OR_FAIL(ctx, dorient.alloc(8 * (size_t)ni * nq)); d_orient = dorient.as<double>(); }
-  }
-  const int nslots = o.cand_q ? o.k : nq;
-  const int shape = split ? split_shape_for(ctx, nx, ny, max_shift, nc) : 0;
-  const size_t per_image = sizeof(bioem_erec) * (size_t)nslots * nc;
-  const int chunk = (int)std::max<size_t>(1, std::min<size_t>(ni, kRecordBudget / per_image));
-  DevMem rec;
-  HIP_OR_FAIL(ctx, rec.alloc(per_image * chunk));
-  const int W = 2 * max_shift + 1;
-  const double log_prior = -std::log((double)nq) - std::log((double)nc) - std::log((double)W * W);
-  const int nchunks = (ni + chunk - 1) / chunk;
-  if (ctx->timing) {
-    while ((int)ctx->ev_start.size() < ctx->ev_used + nchunks) {
-      hipEvent_t a, b;
-      HIP_OR_FAIL(ctx, hipEventCreate(&a));
-      HIP_OR_FAIL(ctx, hipEventCreate(&b));
-      ctx->ev_start.push_back(a);
-      ctx->ev_stop.push_back(b);
-    }
-  }
-  for (int i0 = 0; i0 < ni; i0 += chunk) {
-    const int cn = std::min(chunk, ni - i0);
-    LogpostArgs a{};
-    a.ispec = imgs->spec + len * i0; a.iexpo = imgs->expo + i0; a.istats = imgs->stats + 3 * (size_t)i0; a.ni = cn;
-    a.pspec = proj->spec; a.pexpo = proj->expo; a.nq = nq;
-    a.table = table.as<float>(); a.B = B.as<double>(); a.nc = nc;
-    a.nx = nx; a.ny = ny; a.S = max_shift; a.ldy = spec_ld(ny);
-    a.cand = o.cand_q ? dcand.as<int32_t>() + (size_t)i0 * o.k : nullptr; a.k = o.k;
-    a.rec = rec.as<bioem_erec>();
-    a.kscale = 1.0 / ((double)nx * ny * (double)nx * ny);
-    if (ctx->timing) HIP_OR_FAIL(ctx, hipEventRecord(ctx->ev_start[ctx->ev_used], s));
-    hipError_t e = split ? launch_logpost_split(s, a, o.prec == BIOEM_PREC_SPLIT_BF16, shape) : launch_logpost_f32(s, a);
-    if (ctx->timing && e == hipSuccess) {
-      HIP_OR_FAIL(ctx, hipEventRecord(ctx->ev_stop[ctx->ev_used], s));
-      ++ctx->ev_used;
-      ctx->timed_evals += (double)cn * nslots * nc;
-    }
-    if (e == hipSuccess) {
-      FinalizeArgs f{};
-      f.rec = a.rec; f.ni = cn; f.nslots = nslots; f.nc = nc; f.nq_total = nq; f.nx = nx; f.ny = ny;
-      f.S = max_shift; f.cand = a.cand; f.k = o.k;
-      f.istats = a.istats; f.iexpo = a.iexpo; f.pexpo = proj->expo; f.B = a.B;
-      f.log_prior = log_prior;
-      f.logp = d_logp ? d_logp + i0 : nullptr;
-      f.best = d_best ? d_best + i0 : nullptr;
-      f.orient = d_orient ? d_orient + (size_t)i0 * nq : nullptr;
-      e = launch_finalize(s, f);
-      if (e == hipSuccess && split && f.best) e = launch_best_shift(s, a, f.best);
-    }
-    if (e != hipSuccess) return fail(ctx, BIOEM_EDEVICE, "bioem_logpost: launch failed: %s", hipGetErrorString(e));
-  }
-  if (host_out) {
-    if (logp) HIP_OR_FAIL(ctx, hipMemcpyAsync(logp, d_logp, 8 * (size_t)ni, hipMemcpyDeviceToHost, s));
-    if (best) HIP_OR_FAIL(ctx, hipMemcpyAsync(best, d_best, sizeof(bioem_best) * (size_t)ni, hipMemcpyDeviceToHost, s));
-    if (o.logp_orient)
-      HIP_OR_FAIL(ctx, hipMemcpyAsync(o.logp_orient, d_orient, 8 * (size_t)ni * nq, hipMemcpyDeviceToHost, s));
-  }
+  Job J;
+  bioem_status st = plan_job(ctx, jb, o.prec, o.out_mem, J, "bioem_logpost");
+  if (st != BIOEM_OK) return st;
+  st = run_job(ctx, J, o.prec);
+  if (st != BIOEM_OK) return st;
+  st = copy_out(ctx, J, o.out_mem);
+  if (st != BIOEM_OK) return st;
   // Scratch (table, B, records) is freed on return, so the stream must drain.
-  HIP_OR_FAIL(ctx, hipStreamSynchronize(s));
+  HIP_OR_FAIL(ctx, hipStreamSynchronize(ctx->stream));
+  return BIOEM_OK;
+}
+
+bioem_status bioem_logpost_batch(bioem_ctx* ctx, const bioem_job* jobs, int32_t njobs, int32_t prec,
+                                 int32_t out_mem, int32_t mode) {
+  if (!ctx) return BIOEM_EINVAL;
+  if (!jobs || njobs < 1) return fail(ctx, BIOEM_EINVAL, "bioem_logpost_batch: need njobs >= 1 jobs");
+  if (mode != BIOEM_BATCH_PERSISTENT && mode != BIOEM_BATCH_PER_JOB)
+    return fail(ctx, BIOEM_EINVAL, "bioem_logpost_batch: unknown mode %d", mode);
+  HIP_OR_FAIL(ctx, hipSetDevice(ctx->device));
+  std::vector<Job> J(njobs);
+  for (int j = 0; j < njobs; ++j) {
+    if (jobs[j].reserved) return fail(ctx, BIOEM_EINVAL, "bioem_logpost_batch: job %d reserved must be zero", j);
+    char who[64];
+    std::snprintf(who, sizeof who, "bioem_logpost_batch (job %d)", j);
+    const bioem_status st = plan_job(ctx, jobs[j], prec, out_mem, J[j], who);
+    if (st != BIOEM_OK) return st;
+  }
+  bioem_status st = BIOEM_OK;
+  if (mode == BIOEM_BATCH_PER_JOB || prec == BIOEM_PREC_F32) {
+    for (int j = 0; j < njobs && st == BIOEM_OK; ++j) st = run_job(ctx, J[j], prec);
+  } else {
+    st = run_batch_persistent(ctx, J, prec);
+  }
+  for (int j = 0; j < njobs && st == BIOEM_OK; ++j) st = copy_out(ctx, J[j], out_mem);
+  if (st != BIOEM_OK) return st;
+  HIP_OR_FAIL(ctx, hipStreamSynchronize(ctx->stream));
+  return BIOEM_OK;
+}
+
+bioem_status bioem_set_autotune(bioem_ctx* ctx, int32_t enable) {
+  if (!ctx) return BIOEM_EINVAL;
+  ctx->autotune = enable != 0;
+  return BIOEM_OK;
+}
+
+int32_t bioem_tuning_count(const bioem_ctx* ctx) { return ctx ? (int32_t)ctx->tuned.size() : 0; }
+
+bioem_status bioem_tuning_entry(const bioem_ctx* ctx, int32_t idx, bioem_tuning* out) {
+  if (!ctx || !out || idx < 0 || idx >= (int32_t)ctx->tuned.size()) return BIOEM_EINVAL;
+  *out = ctx->tuned[idx];
   return BIOEM_OK;
 }
 

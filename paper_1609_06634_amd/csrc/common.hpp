@@ -20,6 +20,9 @@ struct bioem_ctx {
   std::vector<hipEvent_t> ev_start, ev_stop;
   int ev_used = 0;
   double timed_evals = 0.0;
+  // tile shapes of the split kernel chosen by the autotuner, per key
+  bool autotune = false;
+  std::vector<bioem_tuning> tuned;
 };
 
 // Half spectra are stored column-major per item: spec[item][m][l] with
@@ -94,8 +97,17 @@ hipError_t launch_logpost_f32(hipStream_t s, const LogpostArgs& a);
 hipError_t launch_best_shift(hipStream_t s, const LogpostArgs& a, bioem_best* best);
 size_t f32_smem_bytes(int nx, int ny, int S);
 constexpr size_t kMaxSmem = 160 * 1024;
-hipError_t launch_logpost_split(hipStream_t s, const LogpostArgs& a, bool bf16, int shape);
+// Split-precision kernel, one job.  shape: compiled launch variant; ti, ts:
+// item tile (images x orientation slots), 0 = default.
+hipError_t launch_logpost_split(hipStream_t s, const LogpostArgs& a, bool bf16, int shape, int ti, int ts);
 int split_num_shapes();
+int split_shape_for_ew(int ew);   // the one-wave-per-SIMD variant with ew CTF sets per item
+// One persistent launch over several jobs; ew in {2, 4} CTF sets per item.
+struct BatchJob {
+  LogpostArgs a;
+  int ew, ti, ts;
+};
+hipError_t launch_logpost_batch(hipStream_t s, const BatchJob* jobs, int njobs, bool bf16);
 bool split_supported(int nx, int ny, int S);
 
 // Per image: FP64 likelihood terms from the per-evaluation records, LSE over

@@ -43,6 +43,7 @@
 // L1; items walk a tiled (image, orientation) order so that concurrently
 // running waves share spectra in L2 and the last-level cache.
 #include <algorithm>
+#include <vector>
 
 #include "common.hpp"
 #include "split_common.hpp"
@@ -51,7 +52,7 @@ namespace bioem {
 
 namespace {
 
-constexpr int kTileImages = 16;     // item tiling for cache reuse
+constexpr int kTileImages = 16;     // default item tile (images x slots) for cache reuse
 constexpr int kTileSlots = 128;
 
 using namespace split;
@@ -62,6 +63,7 @@ struct SplitArgs {
   const uint4* G;       // stage-2 DFT fragments  [MT][NT][2][64]
   int KS, MT;
   int ncg;              // CTF groups per (image, orientation)
+  int ti, ts;           // item tile: images x slots
   int n_ti, n_ts;       // item tiles along images and slots
 };
 
@@ -82,29 +84,22 @@ __device__ __forceinline__ void load_step(Step<EW>& st, const float2* Oc, const 
   for (int e = 0; e < EW; ++e) load8r(Tc[e], l0, st.t[e]);
 }
 
-template <bool BF, int NT, int EW, int WAVES, bool PF>
-__global__ __launch_bounds__(64 * WAVES, 1) void k_logpost_split(SplitArgs sa) {
+// One work item: image i, orientation slot, CTF group cg (EW CTF sets).
+// Fs/Gs: the DFT fragments of this item's box, already in LDS.
+template <bool BF, int NT, int EW, bool PF>
+__device__ __forceinline__ void split_item(const SplitArgs& sa, const uint4* __restrict__ Fs,
+                                           const uint4* __restrict__ Gs, int item) {
   using P = Prec<BF>;
   using V = typename P::V;
-  extern __shared__ uint4 lds[];
   const LogpostArgs& a = sa.a;
   const int KS = sa.KS, MT = sa.MT;
-  const int nF = KS * NT * 2 * 64, nG = MT * NT * 2 * 64;
-  for (int e = threadIdx.x; e < nF + nG; e += 64 * WAVES) lds[e] = e < nF ? sa.F[e] : sa.G[e - nF];
-  __syncthreads();
-  const uint4* Fs = lds;
-  const uint4* Gs = lds + nF;
-
   const int nx = a.nx, ny = a.ny, S = a.S, W = 2 * S + 1;
   const int mh = nx / 2 + 1, half = nx / 2, ldy = a.ldy;
   const size_t len = (size_t)mh * ldy;
   const int lane = threadIdx.x & 63, li = lane & 15, lg = lane >> 4;
-  const int wave = blockIdx.x * WAVES + (threadIdx.x >> 6);
-  const int nwaves = gridDim.x * WAVES;
   const int nslots = a.cand ? a.k : a.nq;
   const int ncg = sa.ncg;
-  const int tile_items = kTileImages * kTileSlots * ncg;
-  const int n_items = sa.n_ti * sa.n_ts * tile_items;
+  const int tile_items = sa.ti * sa.ts * ncg;
   const double n = (double)nx * ny, h = 0.5 * n;
   const float c2 = (float)(h - 1.0);
   const float c2l2e = c2 * 1.4426950408889634f;
@@ -118,13 +113,13 @@ __global__ __launch_bounds__(64 * WAVES, 1) void k_logpost_split(SplitArgs sa) {
   // -(n/2-1) log2(e) times the series of log1p: u - u^2/2 + u^3/3 - u^4/4 + u^5/5
   const float p1 = -c2l2e, p2 = 0.5f * c2l2e, p3 = -c2l2e / 3.0f, p4 = 0.25f * c2l2e, p5 = -0.2f * c2l2e;
 
-  for (int item = wave; item < n_items; item += nwaves) {
+  {
     const int tile = item / tile_items, rr = item - tile * tile_items;
     const int ti = tile / sa.n_ts, ts = tile - ti * sa.n_ts;
     const int cg = rr % ncg, pr = rr / ncg;
-    const int i = ti * kTileImages + pr / kTileSlots;
-    const int slot = ts * kTileSlots + pr % kTileSlots;
-    if (i >= a.ni || slot >= nslots) continue;   // uniform across the wave
+    const int i = ti * sa.ti + pr / sa.ts;
+    const int slot = ts * sa.ts + pr % sa.ts;
+    if (i >= a.ni || slot >= nslots) return;   // uniform across the wave
     const int q = a.cand ? a.cand[(size_t)i * a.k + slot] : slot;
     const float2* O = a.ispec + (size_t)i * len;
     const float2* Pq = a.pspec + (size_t)q * len;
@@ -359,6 +354,60 @@ __global__ __launch_bounds__(64 * WAVES, 1) void k_logpost_split(SplitArgs sa) {
   }
 }
 
+template <bool BF, int NT, int EW, int WAVES, bool PF>
+__global__ __launch_bounds__(64 * WAVES, 1) void k_logpost_split(SplitArgs sa) {
+  extern __shared__ uint4 lds[];
+  const int nF = sa.KS * NT * 2 * 64, nG = sa.MT * NT * 2 * 64;
+  for (int e = threadIdx.x; e < nF + nG; e += 64 * WAVES) lds[e] = e < nF ? sa.F[e] : sa.G[e - nF];
+  __syncthreads();
+  const int wave = blockIdx.x * WAVES + (threadIdx.x >> 6);
+  const int nwaves = gridDim.x * WAVES;
+  const int n_items = sa.n_ti * sa.n_ts * sa.ti * sa.ts * sa.ncg;
+  for (int item = wave; item < n_items; item += nwaves) split_item<BF, NT, EW, PF>(sa, lds, lds + nF, item);
+}
+
+// Persistent form over several jobs (boxes, shift windows, grids) in one
+// launch.  The work list is the concatenation of every job's items in blocks
+// of WAVES consecutive items; workgroup b takes blocks b, b + G, b + 2G, ...
+// so all workgroups sweep the jobs together (the spectra of the current
+// tiles stay shared in the caches) and each receives a near-equal share of
+// every job.  A workgroup reloads the DFT fragments into LDS when it moves
+// on to the next job.
+struct JobDesc {
+  SplitArgs sa;
+  int nt, ew;
+  int block0;   // first work block of the job
+};
+
+template <bool BF, int WAVES>
+__global__ __launch_bounds__(64 * WAVES, 1) void k_logpost_batch(const JobDesc* __restrict__ jobs, int njobs,
+                                                                 int total_blocks) {
+  extern __shared__ uint4 lds[];
+  int cur = -1, nF = 0;
+  for (int blk = blockIdx.x; blk < total_blocks; blk += gridDim.x) {
+    int j = cur < 0 ? 0 : cur;   // blocks only increase, so the job index only advances
+    while (j + 1 < njobs && jobs[j + 1].block0 <= blk) ++j;
+    const JobDesc& jd = jobs[j];
+    if (j != cur) {
+      nF = jd.sa.KS * jd.nt * 128;
+      const int nG = jd.sa.MT * jd.nt * 128;
+      __syncthreads();   // every wave is done with the previous job's fragments
+      for (int e = threadIdx.x; e < nF + nG; e += 64 * WAVES) lds[e] = e < nF ? jd.sa.F[e] : jd.sa.G[e - nF];
+      __syncthreads();
+      cur = j;
+    }
+    const int item = (blk - jd.block0) * WAVES + (threadIdx.x >> 6);
+    switch (jd.nt * 8 + jd.ew) {   // uniform across the workgroup
+      case 1 * 8 + 2: split_item<BF, 1, 2, false>(jd.sa, lds, lds + nF, item); break;
+      case 1 * 8 + 4: split_item<BF, 1, 4, false>(jd.sa, lds, lds + nF, item); break;
+      case 2 * 8 + 2: split_item<BF, 2, 2, false>(jd.sa, lds, lds + nF, item); break;
+      case 2 * 8 + 4: split_item<BF, 2, 4, false>(jd.sa, lds, lds + nF, item); break;
+      case 3 * 8 + 2: split_item<BF, 3, 2, false>(jd.sa, lds, lds + nF, item); break;
+      default: split_item<BF, 3, 4, false>(jd.sa, lds, lds + nF, item); break;
+    }
+  }
+}
+
 // Fragment tables of the two DFT matrices, split into hi/lo parts.
 template <bool BF>
 __global__ void k_split_tables(int nx, int ny, int S, int NT, int KS, int MT, uint4* __restrict__ F,
@@ -440,7 +489,7 @@ hipError_t launch_shape(hipStream_t s, const SplitArgs& sa, size_t smem, int ncu
   hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
   if (e != hipSuccess) return e;
-  const long n_items = (long)sa.n_ti * sa.n_ts * kTileImages * kTileSlots * sa.ncg;
+  const long n_items = (long)sa.n_ti * sa.n_ts * sa.ti * sa.ts * sa.ncg;
   const long want = (n_items + WAVES - 1) / WAVES;
   const int grid = (int)std::min<long>(want, (long)ncu);
   hipLaunchKernelGGL(kern, dim3(grid), dim3(64 * WAVES), smem, s, sa);
@@ -467,14 +516,25 @@ bool split_supported(int nx, int ny, int S) {
 
 int split_num_shapes() { return kNumShapes; }
 
-static int split_ctf_groups(int nc, int shape) { return (nc + kShapes[shape].ew - 1) / kShapes[shape].ew; }
+static int split_ctf_groups(int nc, int ew) { return (nc + ew - 1) / ew; }
 
-hipError_t launch_logpost_split(hipStream_t s, const LogpostArgs& a, bool bf16, int shape) {
-  if (shape < 0 || shape >= kNumShapes) return hipErrorInvalidValue;
+static int device_cus() {
+  int dev = 0, ncu = 256;
+  if (hipGetDevice(&dev) == hipSuccess) {
+    int v = 0;
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && v > 0) ncu = v;
+  }
+  return ncu;
+}
+
+// Fragment tables (stream-ordered allocation, freed by the caller with
+// hipFreeAsync) and the argument block of one job.
+static hipError_t make_split_args(hipStream_t s, const LogpostArgs& a, bool bf16, int ew, int ti, int ts,
+                                  SplitArgs& sa, uint4*& tabs) {
   const int NT = nt_for(a.S);
   const int KS = (a.ny + 31) / 32, MT = (a.nx / 2 + 15) / 16;
   const int nF = KS * NT * 2 * 64, nG = MT * NT * 2 * 64;
-  uint4* tabs = nullptr;
+  tabs = nullptr;
   hipError_t e = hipMallocAsync(reinterpret_cast<void**>(&tabs), sizeof(uint4) * (nF + nG), s);
   if (e != hipSuccess) return e;
   const int nt = nF + nG;
@@ -484,27 +544,83 @@ hipError_t launch_logpost_split(hipStream_t s, const LogpostArgs& a, bool bf16, 
   else
     hipLaunchKernelGGL(k_split_tables<false>, dim3((nt + 255) / 256), dim3(256), 0, s, a.nx, a.ny, a.S, NT, KS, MT,
                        tabs, tabs + nF);
-  SplitArgs sa;
+  sa = SplitArgs{};
   sa.a = a;
   sa.F = tabs;
   sa.G = tabs + nF;
   sa.KS = KS;
   sa.MT = MT;
-  sa.ncg = split_ctf_groups(a.nc, shape);
+  sa.ncg = split_ctf_groups(a.nc, ew);
   const int nslots = a.cand ? a.k : a.nq;
-  sa.n_ti = (a.ni + kTileImages - 1) / kTileImages;
-  sa.n_ts = (nslots + kTileSlots - 1) / kTileSlots;
-  int dev = 0, ncu = 256;
-  if (hipGetDevice(&dev) == hipSuccess) {
-    int v = 0;
-    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && v > 0) ncu = v;
+  sa.ti = ti > 0 ? ti : kTileImages;
+  sa.ts = ts > 0 ? ts : kTileSlots;
+  sa.n_ti = (a.ni + sa.ti - 1) / sa.ti;
+  sa.n_ts = (nslots + sa.ts - 1) / sa.ts;
+  return hipGetLastError();
+}
+
+hipError_t launch_logpost_split(hipStream_t s, const LogpostArgs& a, bool bf16, int shape, int ti, int ts) {
+  if (shape < 0 || shape >= kNumShapes) return hipErrorInvalidValue;
+  SplitArgs sa;
+  uint4* tabs = nullptr;
+  hipError_t e = make_split_args(s, a, bf16, kShapes[shape].ew, ti, ts, sa, tabs);
+  if (e == hipSuccess) {
+    const int NT = nt_for(a.S), ncu = device_cus();
+    const size_t smem = split_smem(a.nx, a.ny, a.S);
+    if (NT == 1) e = bf16 ? launch_nt<true, 1>(s, sa, smem, ncu, shape) : launch_nt<false, 1>(s, sa, smem, ncu, shape);
+    else if (NT == 2) e = bf16 ? launch_nt<true, 2>(s, sa, smem, ncu, shape) : launch_nt<false, 2>(s, sa, smem, ncu, shape);
+    else e = bf16 ? launch_nt<true, 3>(s, sa, smem, ncu, shape) : launch_nt<false, 3>(s, sa, smem, ncu, shape);
   }
-  const size_t smem = split_smem(a.nx, a.ny, a.S);
-  if (NT == 1) e = bf16 ? launch_nt<true, 1>(s, sa, smem, ncu, shape) : launch_nt<false, 1>(s, sa, smem, ncu, shape);
-  else if (NT == 2) e = bf16 ? launch_nt<true, 2>(s, sa, smem, ncu, shape) : launch_nt<false, 2>(s, sa, smem, ncu, shape);
-  else e = bf16 ? launch_nt<true, 3>(s, sa, smem, ncu, shape) : launch_nt<false, 3>(s, sa, smem, ncu, shape);
-  const hipError_t f = hipFreeAsync(tabs, s);
+  const hipError_t f = tabs ? hipFreeAsync(tabs, s) : hipSuccess;
   return e != hipSuccess ? e : f;
+}
+
+int split_shape_for_ew(int ew) {
+  for (int k = 0; k < kNumShapes; ++k)
+    if (kShapes[k].ew == ew && kShapes[k].waves == 4 && !kShapes[k].pf) return k;
+  return 3;
+}
+
+hipError_t launch_logpost_batch(hipStream_t s, const BatchJob* jobs, int njobs, bool bf16) {
+  constexpr int kWaves = 4;
+  if (njobs < 1) return hipErrorInvalidValue;
+  std::vector<JobDesc> desc(njobs);
+  std::vector<uint4*> tabs(njobs, nullptr);
+  hipError_t e = hipSuccess;
+  long blocks = 0;
+  size_t smem = 0;
+  for (int j = 0; j < njobs && e == hipSuccess; ++j) {
+    const int ew = jobs[j].ew == 2 ? 2 : 4;
+    e = make_split_args(s, jobs[j].a, bf16, ew, jobs[j].ti, jobs[j].ts, desc[j].sa, tabs[j]);
+    desc[j].nt = nt_for(jobs[j].a.S);
+    desc[j].ew = ew;
+    desc[j].block0 = (int)blocks;
+    const SplitArgs& sa = desc[j].sa;
+    const long items = (long)sa.n_ti * sa.n_ts * sa.ti * sa.ts * sa.ncg;
+    blocks += (items + kWaves - 1) / kWaves;
+    smem = std::max(smem, split_smem(jobs[j].a.nx, jobs[j].a.ny, jobs[j].a.S));
+  }
+  JobDesc* djobs = nullptr;
+  if (e == hipSuccess && blocks > 0x7fffffffL) e = hipErrorInvalidValue;
+  if (e == hipSuccess) e = hipMallocAsync(reinterpret_cast<void**>(&djobs), sizeof(JobDesc) * njobs, s);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(djobs, desc.data(), sizeof(JobDesc) * njobs, hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) {
+    auto kern = bf16 ? k_logpost_batch<true, kWaves> : k_logpost_batch<false, kWaves>;
+    e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern), hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)smem);
+    if (e == hipSuccess) {
+      const int grid = (int)std::min<long>(blocks, (long)device_cus());
+      hipLaunchKernelGGL(kern, dim3(grid), dim3(64 * kWaves), smem, s, djobs, njobs, (int)blocks);
+      e = hipGetLastError();
+    }
+  }
+  // the host descriptor copy must not be reused before the copy has run
+  const hipError_t sy = hipStreamSynchronize(s);
+  if (djobs) (void)hipFreeAsync(djobs, s);
+  for (uint4* t : tabs)
+    if (t) (void)hipFreeAsync(t, s);
+  return e != hipSuccess ? e : sy;
 }
 
 }  // namespace bioem

@@ -8,31 +8,33 @@ namespace bioem {
 
 namespace {
 
-constexpr int kProjRows = 16;      // image rows per projection workgroup
-constexpr int kProjSpheres = 8;    // spheres staged in LDS per step
-constexpr int kProjThreads = 256;
-constexpr int kProjMaxPix = kProjRows * kMaxBox / kProjThreads;
+constexpr int kProjWaves = 4;      // waves per projection workgroup (one per SIMD)
+constexpr int kProjTiles = 25;     // 16x16 output tiles per wave
+constexpr int kProjChunk = 8;      // spheres per LDS stage (two MFMA K-steps)
+constexpr int kProjSeg = 63;       // pixels per wave segment (64 boundaries)
 
-// Integral over one pixel [u - h, u + h] of a unit 1-D Gaussian centred at 0,
-// with erfc used on whichever side keeps the difference free of cancellation.
-BIOEM_DEV double pixel_integral(double u, double h, double inv_s2sig) {
-  const double a = (u - h) * inv_s2sig, b = (u + h) * inv_s2sig;
-  if (a > 0.0) return 0.5 * (erfc(a) - erfc(b));
-  if (b < 0.0) return 0.5 * (erfc(-b) - erfc(-a));
-  return 0.5 * (erf(b) - erf(a));
-}
+typedef double d4 __attribute__((ext_vector_type(4)));
 
-// Eq. (ideal): I0[k][j] = sum_a w_a Ey_a[k] Ex_a[j] for rotated spheres.
-// grid: (ceil(ny / kProjRows), nq); block: kProjThreads.
-__global__ __launch_bounds__(kProjThreads) void k_project(const double* __restrict__ spheres, int ns,
-                                                          const double* __restrict__ quats, int nx,
-                                                          int ny, double pixel, double* __restrict__ out) {
-  __shared__ double ex[kProjSpheres][kMaxBox];
-  __shared__ double ey[kProjSpheres][kProjRows];
-  __shared__ double rot[9];
+// Eq. (ideal) with each Gaussian integrated over the pixel:
+//   I0[k][j] = sum_a w_a Ey_a[k] Ex_a[j],
+//   Ex_a[j] = integral over pixel j of the unit 1-D Gaussian of width sigma_a
+//             centred at the rotated x_a (likewise Ey),
+// i.e. a [ny x ns] x [ns x nx] FP64 product per orientation, computed on the
+// FP64 matrix cores (v_mfma_f64_16x16x4_f64) from factors built in LDS.
+// A pixel integral is (erf(b) - erf(a))/2 over its two boundaries; each
+// boundary's erfc(|z|) is evaluated once and shared with the neighbouring
+// pixel, and the difference is taken on the side that avoids cancellation.
+// A workgroup owns a band of whole 16-row tile rows (as many as its waves'
+// accumulators hold) and builds the y factors of those rows only.
+// grid: (bands, nq); block: 64 * kProjWaves.
+__global__ __launch_bounds__(64 * kProjWaves, 1) void k_project(const double* __restrict__ spheres, int ns,
+                                                             const double* __restrict__ quats, int nx,
+                                                             int ny, double pixel, double* __restrict__ out) {
+  __shared__ double ex[kProjChunk][kMaxBox];
+  __shared__ double ey[kProjChunk][kMaxBox];
+  __shared__ double rot[6];
   const int q = blockIdx.y;
-  const int k0 = blockIdx.x * kProjRows;
-  const int tid = threadIdx.x;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   if (tid == 0) {
     double w = quats[4 * q + 0], x = quats[4 * q + 1], y = quats[4 * q + 2], z = quats[4 * q + 3];
     const double inv = 1.0 / sqrt(w * w + x * x + y * y + z * z);
@@ -41,47 +43,85 @@ __global__ __launch_bounds__(kProjThreads) void k_project(const double* __restri
     rot[0] = 1 - 2 * (y * y + z * z); rot[1] = 2 * (x * y - w * z); rot[2] = 2 * (x * z + w * y);
     rot[3] = 2 * (x * y + w * z); rot[4] = 1 - 2 * (x * x + z * z); rot[5] = 2 * (y * z - w * x);
   }
-  __syncthreads();
-  const int rows = min(kProjRows, ny - k0);
-  const int npix = rows * nx;
-  double acc[kProjMaxPix];
-#pragma unroll
-  for (int r = 0; r < kProjMaxPix; ++r) acc[r] = 0.0;
+  const int tcols = (nx + 15) / 16, trows = (ny + 15) / 16;
+  const int rb = (kProjWaves * kProjTiles) / tcols;            // tile rows per band
+  const int tr0 = blockIdx.x * rb, tr1 = min(trows, tr0 + rb);
+  const int band0 = tr0 * tcols, band1 = tr1 * tcols;
+  const int nxp = 16 * tcols, ky0 = 16 * tr0, nyb = 16 * (tr1 - tr0);
+  const int segx = (nxp + kProjSeg - 1) / kProjSeg, segy = (nyb + kProjSeg - 1) / kProjSeg;
+  const int tasks = kProjChunk * (segx + segy);
   const double h = 0.5 * pixel;
-  for (int a0 = 0; a0 < ns; a0 += kProjSpheres) {
-    const int na = min(kProjSpheres, ns - a0);
-    for (int e = tid; e < na * nx; e += kProjThreads) {
-      const int a = e / nx, j = e - a * nx;
-      const double* sp = spheres + 5 * (a0 + a);
-      const double xr = rot[0] * sp[0] + rot[1] * sp[1] + rot[2] * sp[2];
-      const double inv = 1.0 / (sqrt(2.0) * sp[3]);
-      ex[a][j] = pixel_integral((j - nx / 2) * pixel - xr, h, inv);
-    }
-    for (int e = tid; e < na * rows; e += kProjThreads) {
-      const int a = e / rows, kk = e - a * rows;
-      const double* sp = spheres + 5 * (a0 + a);
-      const double yr = rot[3] * sp[0] + rot[4] * sp[1] + rot[5] * sp[2];
-      const double inv = 1.0 / (sqrt(2.0) * sp[3]);
-      ey[a][kk] = sp[4] * pixel_integral((k0 + kk - ny / 2) * pixel - yr, h, inv);
+  d4 acc[kProjTiles];
+#pragma unroll
+  for (int t = 0; t < kProjTiles; ++t) acc[t] = d4{0.0, 0.0, 0.0, 0.0};
+  __syncthreads();
+  for (int a0 = 0; a0 < ns; a0 += kProjChunk) {
+    // factors of this chunk: one (sphere, axis, 63-pixel segment) per wave pass
+    for (int task = wave; task < tasks; task += kProjWaves) {
+      const int a = task / (segx + segy), r = task - a * (segx + segy);
+      const bool yaxis = r >= segx;
+      // pixels [lo, hi) of this axis are built; the segment starts at p0
+      const int lo = yaxis ? ky0 : 0, hi = yaxis ? ky0 + nyb : nxp;
+      const int p0 = lo + kProjSeg * (yaxis ? r - segx : r);
+      const int n = yaxis ? ny : nx;
+      double c = 0.0, inv = 0.0, wgt = 0.0;
+      const bool real = a0 + a < ns;
+      if (real) {
+        const double* sp = spheres + 5 * (a0 + a);
+        c = yaxis ? rot[3] * sp[0] + rot[4] * sp[1] + rot[5] * sp[2]
+                  : rot[0] * sp[0] + rot[1] * sp[1] + rot[2] * sp[2];
+        inv = 1.0 / (sqrt(2.0) * sp[3]);
+        wgt = yaxis ? sp[4] : 1.0;
+      }
+      // boundary p0 + lane lies at the lower edge of pixel p0 + lane
+      const double zb = (((p0 + lane) - n / 2) * pixel - h - c) * inv;
+      const double az = fabs(zb);
+      const double eb = az < 27.3 ? erfc(az) : 0.0;   // erfc(27.3) < 2^-1074
+      const double zn = __shfl_down(zb, 1, 64);
+      const double en = __shfl_down(eb, 1, 64);
+      const int p = p0 + lane;
+      if (lane < kProjSeg && p < hi) {
+        double v = 0.0;
+        if (real && p < n) {
+          if (zb > 0.0) v = 0.5 * (eb - en);           // both boundaries above the centre
+          else if (zn < 0.0) v = 0.5 * (en - eb);      // both below
+          else v = 0.5 * ((1.0 - eb) + (1.0 - en));    // straddles the centre
+        }
+        if (yaxis) ey[a][p - ky0] = wgt * v;
+        else ex[a][p] = wgt * v;
+      }
     }
     __syncthreads();
 #pragma unroll
-    for (int r = 0; r < kProjMaxPix; ++r) {
-      const int p = tid + r * kProjThreads;
-      if (p < npix) {
-        const int kk = p / nx, j = p - kk * nx;
-        double s = acc[r];
-        for (int a = 0; a < na; ++a) s = fma(ey[a][kk], ex[a][j], s);
-        acc[r] = s;
+    for (int ks = 0; ks < kProjChunk / 4; ++ks) {
+      const int kk = 4 * ks + (lane >> 4), li = lane & 15;
+#pragma unroll
+      for (int t = 0; t < kProjTiles; ++t) {
+        const int tile = band0 + wave + kProjWaves * t;
+        if (tile < band1) {   // uniform across the wave
+          const int tr = tile / tcols, tc = tile - tr * tcols;
+          const double av = ey[kk][16 * (tr - tr0) + li];
+          const double bv = ex[kk][16 * tc + li];
+          acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc[t], 0, 0, 0);
+        }
       }
     }
     __syncthreads();
   }
-  double* dst = out + ((size_t)q * ny + k0) * nx;
+  // D[i][j] of a 16x16 tile sits in lane j + 16 (i / 4), element i % 4
+  double* dst = out + (size_t)q * ny * nx;
 #pragma unroll
-  for (int r = 0; r < kProjMaxPix; ++r) {
-    const int p = tid + r * kProjThreads;
-    if (p < npix) dst[p] = acc[r];
+  for (int t = 0; t < kProjTiles; ++t) {
+    const int tile = band0 + wave + kProjWaves * t;
+    if (tile < band1) {
+      const int tr = tile / tcols, tc = tile - tr * tcols;
+      const int j = 16 * tc + (lane & 15);
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int k = 16 * tr + 4 * (lane >> 4) + r;
+        if (k < ny && j < nx) dst[(size_t)k * nx + j] = acc[t][r];
+      }
+    }
   }
 }
 
@@ -365,8 +405,9 @@ static hipError_t last() { return hipGetLastError(); }
 
 hipError_t launch_project_images(hipStream_t s, const double* spheres, int ns, const double* quats,
                                  int nq, int nx, int ny, double pixel, double* out_i0) {
-  dim3 grid((ny + kProjRows - 1) / kProjRows, nq);
-  hipLaunchKernelGGL(k_project, grid, dim3(kProjThreads), 0, s, spheres, ns, quats, nx, ny, pixel, out_i0);
+  const int rb = (kProjWaves * kProjTiles) / ((nx + 15) / 16);
+  dim3 grid(((ny + 15) / 16 + rb - 1) / rb, nq);
+  hipLaunchKernelGGL(k_project, grid, dim3(64 * kProjWaves), 0, s, spheres, ns, quats, nx, ny, pixel, out_i0);
   return last();
 }
 

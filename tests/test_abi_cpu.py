@@ -51,6 +51,17 @@ def test_struct_layouts(lib):
     assert ctypes.sizeof(P.bindings.Best) == 32
     assert P.BEST_DTYPE.itemsize == 32
     assert ctypes.sizeof(P.bindings.Opts) == 48
+    assert ctypes.sizeof(P.bindings.Job) == 80
+    assert ctypes.sizeof(P.bindings.Tuning) == 48
+    assert ctypes.sizeof(P.bindings.CnnArch) == 32
+
+
+def test_null_context_calls(lib):
+    assert lib.bioem_set_autotune(None, 1) == P.bindings.BIOEM_EINVAL
+    assert lib.bioem_tuning_count(None) == 0
+    assert lib.bioem_logpost_batch(None, None, 0, 2, 0, 0) == P.bindings.BIOEM_EINVAL
+    assert lib.bioem_cnn_create(None, None, None) == P.bindings.BIOEM_EINVAL
+    assert lib.bioem_cnn_num_params(None) == 0
 
 
 def test_create_without_device_fails_cleanly(lib):

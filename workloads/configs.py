@@ -212,5 +212,23 @@ def make_workload(k: int, n_images: Optional[int] = None) -> Workload:
     return wl
 
 
+def proposal_training_images(n: int, stream: int = 2, nq_grid: Optional[int] = None) -> SizeClass:
+    """Per-image parameters of n training images for the learned proposal
+    (the 128^2 workload's model, grids and image distribution, drawn from the
+    separate stream [160906634, 5, stream]; the held-out images are the
+    workload's own).  ``nq_grid`` keeps the first orientations of the grid."""
+    base = make_workload(5, n_images=1).classes[0]
+    rng = np.random.default_rng([BASE_SEED, 5, stream])
+    img_quat = shoemake_quaternions(rng, n)
+    S = base.max_shift
+    img_shift = rng.integers(-S, S + 1, size=(n, 2)).astype(np.int32)
+    img_ctf = _img_ctf_uniform(50.0, 50.0)(rng, n)
+    quats = base.quats if nq_grid is None else base.quats[:nq_grid]
+    return SizeClass(nx=base.nx, ny=base.ny, pixel_A=base.pixel_A, max_shift=S, quats=quats,
+                     ctf=base.ctf, img_model=np.zeros(n, np.int32), img_quat=img_quat,
+                     img_shift=img_shift, img_ctf=img_ctf, img_norm=np.tile([1.0, 0.0], (n, 1)),
+                     snr=base.snr, noise_seed=(BASE_SEED, 5, stream, 1))
+
+
 CONFIGS = {1: "64^2 small", 2: "224^2 paper-shaped", 3: "64^2 split-bf16",
            4: "mixed sizes, two models", 5: "128^2 learned proposal"}
