@@ -128,9 +128,14 @@ def main() -> int:
     ap.add_argument("--images", type=int, default=1000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", default="2x8x2")
-    ap.add_argument("--workload", default="paper224", choices=["paper224", "mixed"],
+    ap.add_argument("--workload", default="paper224", choices=["paper224", "mixed", "proposal"],
                     help="paper224: 224^2, 1000 images x 4608 orientations x 8 CTF sets (default); "
-                         "mixed: 96/128/180/224 px classes x two models in one persistent launch")
+                         "mixed: 96/128/180/224 px classes x two models in one persistent launch; "
+                         "proposal: 128^2 x 36,864 orientations with the learned top-K proposal")
+    ap.add_argument("--train-images", type=int, default=100000)
+    ap.add_argument("--epochs", type=int, default=4)
+    ap.add_argument("--topk", type=int, default=256)
+    ap.add_argument("--tau", type=float, default=0.5)
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB three times (the reference "
                          "kernel for scaling HBM traffic counters) and exit")
@@ -161,6 +166,8 @@ def main() -> int:
     ctx = P.Context(0)
     if args.workload == "mixed":
         return run_mixed(args, P, ctx, torch, dev)
+    if args.workload == "proposal":
+        return run_proposal(args, P, ctx, torch, dev)
 
     # ---- inputs, resident in HBM ------------------------------------------------
     log("generating the 224^2 workload")
@@ -339,6 +346,84 @@ def run_mixed(args, P, ctx, torch, dev) -> int:
             "persistent_over_per_job": q["dt"] / p["dt"],
             "tuning": ctx.tunings()}
     print(json.dumps(line), flush=True)
+    ctx.close()
+    return 0
+
+
+def run_proposal(args, P, ctx, torch, dev) -> int:
+    """128^2 images over 36,864 orientations x 4 CTF sets: the exhaustive
+    posterior against the learned proposal (network top-K orientations per
+    image, exhaustive fallback below the softmax-mass threshold).  The
+    network is trained here first, on images labelled by the exhaustive
+    posterior (not timed).  value = effective evals/s of the proposal path
+    (all images x full grid / its wall time, network included)."""
+    import numpy as np
+    from paper_1609_06634_amd import proposal as PR
+    from workloads import make_workload, proposal_training_images
+    held_n = args.images
+    wl = make_workload(5, n_images=held_n)
+    held = wl.classes[0]
+    model = wl.models[0]
+    model_dev = torch.from_numpy(model).to(dev)
+    nq, nc, S = len(held.quats), len(held.ctf), held.max_shift
+    proj = P.project(ctx, model_dev, torch.from_numpy(held.quats).to(dev), held.nx, held.ny, held.pixel_A)
+    ctf = torch.from_numpy(held.ctf).to(dev)
+    log(f"training set: {args.train_images} images labelled over {nq} orientations x {nc} CTF sets")
+    tr = proposal_training_images(args.train_images)
+    data = PR.make_training_set(ctx, model, tr, proj, T=32, chunk=2000, log=log)
+    net = P.Net(ctx, held.nx, 32, 64, 128, 128, 32, nq)
+    net.set_params(PR.init_params(net, held.quats))
+    t0 = time.perf_counter()
+    losses = PR.train(net, data, epochs=args.epochs, batch=256, lr=1e-3, log=log)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    label_s, label_mass = data.seconds, float(np.median(data.mass))
+    del data
+    imgs = PR.render_class_images(ctx, model_dev, held, 0, held_n)
+    torch.cuda.synchronize()
+    evals = held_n * nq * nc
+
+    def exhaustive():
+        im = P.prepare_images(ctx, imgs)
+        out = P.logpost(ctx, proj, im, ctf, S, prec=args.prec, device_out=True)
+        im.free()
+        return out["logp"]
+
+    exhaustive()
+    PR.score_with_proposal(ctx, net, proj, imgs, ctf, S, K=args.topk, tau=args.tau, prec=args.prec)
+    t_ex, t_pr = [], []
+    for k in range(args.steps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ref = exhaustive()
+        torch.cuda.synchronize()
+        t_ex.append(time.perf_counter() - t0)
+        r = PR.score_with_proposal(ctx, net, proj, imgs, ctf, S, K=args.topk, tau=args.tau, prec=args.prec)
+        t_pr.append(r.seconds)
+        log(f"step {k + 1}/{args.steps}: exhaustive {t_ex[-1] * 1e3:.1f} ms, proposal {r.seconds * 1e3:.1f} ms")
+    ref = ref.cpu().numpy()
+    d = ref - r.logp
+    tex, tpr = float(np.mean(t_ex)), float(np.mean(t_pr))
+    line = {"metric": METRIC + " (effective, learned top-K proposal)", "value": evals / tpr,
+            "unit": "evals/s", "n_gpus": 1, "steps": args.steps, "warmup": 1, "ms_per_step": tpr * 1e3,
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+            "dtype": "bf16 network; f16x2 split posterior on MFMA (f32 acc), f64 likelihood",
+            "data": "synthetic",
+            "config": {"workload": f"128x128 px at 2.31 A/px, 1000-sphere model, {held_n} held-out images x "
+                                   f"{nq} orientations x {nc} CTF sets, shifts +-{S}; top-{args.topk} "
+                                   f"proposal, exhaustive fallback below mass {args.tau}",
+                       "evals_per_step": evals, "prec": args.prec},
+            "exhaustive": {"value": evals / tex, "ms_per_step": tex * 1e3},
+            "speedup_vs_exhaustive": tex / tpr,
+            "dlogp": {"max": float(d.max()), "median": float(np.median(d)),
+                      "frac_le_0.1": float(np.mean(d <= 0.1)), "min": float(d.min())},
+            "fallback_fraction": float(r.fallback.mean()),
+            "evals_computed_fraction": r.evals / evals,
+            "training": {"images": args.train_images, "epochs": args.epochs, "seconds": t_train,
+                         "label_seconds": label_s, "loss_per_epoch": losses,
+                         "label_mass_top32_median": label_mass}}
+    print(json.dumps(line), flush=True)
+    net.close()
     ctx.close()
     return 0
 

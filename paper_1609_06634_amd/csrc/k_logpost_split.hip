@@ -86,7 +86,12 @@ __device__ __forceinline__ void load_step(Step<EW>& st, const float2* Oc, const 
 
 // One work item: image i, orientation slot, CTF group cg (EW CTF sets).
 // Fs/Gs: the DFT fragments of this item's box, already in LDS.
-template <bool BF, int NT, int EW, bool PF>
+// Load schedules of the stage-1 K loop.
+constexpr int kLoadNext = 0;   // one register set, next step loaded once consumed
+constexpr int kLoadPing = 1;   // two register sets in ping-pong
+constexpr int kLoadNone = 2;   // each step loaded just before use
+
+template <bool BF, int NT, int EW, int LM>
 __device__ __forceinline__ void split_item(const SplitArgs& sa, const uint4* __restrict__ Fs,
                                            const uint4* __restrict__ Gs, int item) {
   using P = Prec<BF>;
@@ -154,7 +159,9 @@ __device__ __forceinline__ void split_item(const SplitArgs& sa, const uint4* __r
 #pragma unroll
         for (int e = 0; e < EW; ++e) Tc[e] = a.table + (size_t)min(c0 + e, a.nc - 1) * len + (size_t)col * ldy;
         const bool pk = mt == 0;             // slot 0 of this tile carries columns 0 and nx/2
-        auto body = [&](const Step<EW>& cur, int ks) {
+        // prep: the K-step's conjugate products, CTF-weighted and split
+        // into hi/lo operands (consumes the loaded step); mma: its products
+        auto prep = [&](const Step<EW>& cur, int ks, V (&zrh)[EW], V (&zrl)[EW], V (&zih)[EW], V (&zil)[EW]) {
           const int l0 = 32 * ks + 8 * lg;
           float2 w0[8];
 #pragma unroll
@@ -194,12 +201,13 @@ __device__ __forceinline__ void split_item(const SplitArgs& sa, const uint4* __r
               }
             }
           }
-          V zrh[EW], zrl[EW], zih[EW], zil[EW];
 #pragma unroll
           for (int e = 0; e < EW; ++e) {
             split8<BF>(zr[e], zrh[e], zrl[e]);
             split8<BF>(zi[e], zih[e], zil[e]);
           }
+        };
+        auto mma = [&](int ks, const V (&zrh)[EW], const V (&zrl)[EW], const V (&zih)[EW], const V (&zil)[EW]) {
           V fh[NT], fl[NT];
 #pragma unroll
           for (int ct = 0; ct < NT; ++ct) {
@@ -230,7 +238,12 @@ __device__ __forceinline__ void split_item(const SplitArgs& sa, const uint4* __r
               acc1[e][ct][1] = P::mma(zil[e], fh[ct], acc1[e][ct][1]);
             }
         };
-        if constexpr (PF) {
+        auto body = [&](const Step<EW>& cur, int ks) {
+          V zrh[EW], zrl[EW], zih[EW], zil[EW];
+          prep(cur, ks, zrh, zrl, zih, zil);
+          mma(ks, zrh, zrl, zih, zil);
+        };
+        if constexpr (LM == kLoadPing) {
           // two register sets in ping-pong: the loads of the next K-step are
           // in flight while this one computes, with no copies between sets
           Step<EW> sa0, sa1;
@@ -243,11 +256,23 @@ __device__ __forceinline__ void split_item(const SplitArgs& sa, const uint4* __r
               body(sa1, ks + 1);
             }
           }
-        } else {
+        } else if constexpr (LM == kLoadNone) {
           for (int ks = 0; ks < KS; ++ks) {
             Step<EW> st;
             load_step<EW>(st, Oc, Pc, Tc, 32 * ks + 8 * lg);
             body(st, ks);
+          }
+        } else {
+          // one register set: once a step's loads are consumed by prep, the
+          // same registers take the next step's loads, which stay in flight
+          // during this step's matrix products
+          Step<EW> st;
+          load_step<EW>(st, Oc, Pc, Tc, 8 * lg);
+          for (int ks = 0; ks < KS; ++ks) {
+            V zrh[EW], zrl[EW], zih[EW], zil[EW];
+            prep(st, ks, zrh, zrl, zih, zil);
+            if (ks + 1 < KS) load_step<EW>(st, Oc, Pc, Tc, 32 * (ks + 1) + 8 * lg);
+            mma(ks, zrh, zrl, zih, zil);
           }
         }
         // stage 2: this m-tile is one K-step of the c2r GEMM
@@ -354,7 +379,7 @@ __device__ __forceinline__ void split_item(const SplitArgs& sa, const uint4* __r
   }
 }
 
-template <bool BF, int NT, int EW, int WAVES, bool PF>
+template <bool BF, int NT, int EW, int WAVES, int LM>
 __global__ __launch_bounds__(64 * WAVES, 1) void k_logpost_split(SplitArgs sa) {
   extern __shared__ uint4 lds[];
   const int nF = sa.KS * NT * 2 * 64, nG = sa.MT * NT * 2 * 64;
@@ -363,7 +388,7 @@ __global__ __launch_bounds__(64 * WAVES, 1) void k_logpost_split(SplitArgs sa) {
   const int wave = blockIdx.x * WAVES + (threadIdx.x >> 6);
   const int nwaves = gridDim.x * WAVES;
   const int n_items = sa.n_ti * sa.n_ts * sa.ti * sa.ts * sa.ncg;
-  for (int item = wave; item < n_items; item += nwaves) split_item<BF, NT, EW, PF>(sa, lds, lds + nF, item);
+  for (int item = wave; item < n_items; item += nwaves) split_item<BF, NT, EW, LM>(sa, lds, lds + nF, item);
 }
 
 // Persistent form over several jobs (boxes, shift windows, grids) in one
@@ -398,12 +423,12 @@ __global__ __launch_bounds__(64 * WAVES, 1) void k_logpost_batch(const JobDesc* 
     }
     const int item = (blk - jd.block0) * WAVES + (threadIdx.x >> 6);
     switch (jd.nt * 8 + jd.ew) {   // uniform across the workgroup
-      case 1 * 8 + 2: split_item<BF, 1, 2, false>(jd.sa, lds, lds + nF, item); break;
-      case 1 * 8 + 4: split_item<BF, 1, 4, false>(jd.sa, lds, lds + nF, item); break;
-      case 2 * 8 + 2: split_item<BF, 2, 2, false>(jd.sa, lds, lds + nF, item); break;
-      case 2 * 8 + 4: split_item<BF, 2, 4, false>(jd.sa, lds, lds + nF, item); break;
-      case 3 * 8 + 2: split_item<BF, 3, 2, false>(jd.sa, lds, lds + nF, item); break;
-      default: split_item<BF, 3, 4, false>(jd.sa, lds, lds + nF, item); break;
+      case 1 * 8 + 2: split_item<BF, 1, 2, kLoadNone>(jd.sa, lds, lds + nF, item); break;
+      case 1 * 8 + 4: split_item<BF, 1, 4, kLoadNone>(jd.sa, lds, lds + nF, item); break;
+      case 2 * 8 + 2: split_item<BF, 2, 2, kLoadNone>(jd.sa, lds, lds + nF, item); break;
+      case 2 * 8 + 4: split_item<BF, 2, 4, kLoadNone>(jd.sa, lds, lds + nF, item); break;
+      case 3 * 8 + 2: split_item<BF, 3, 2, kLoadNone>(jd.sa, lds, lds + nF, item); break;
+      default: split_item<BF, 3, 4, kLoadNone>(jd.sa, lds, lds + nF, item); break;
     }
   }
 }
@@ -475,17 +500,17 @@ size_t split_smem(int nx, int ny, int S) {
 
 // Launch shapes of the split kernel: CTF sets per wave item, waves per
 // workgroup (4 = one wave per SIMD with up to 512 registers, 8 = two per SIMD
-// with up to 256) and register prefetch of the next K-step.
+// with up to 256) and the load schedule of the K loop.
 struct Shape {
-  int ew, waves;
-  bool pf;
+  int ew, waves, lm;
 };
-constexpr Shape kShapes[] = {{2, 4, true}, {2, 8, false}, {1, 8, false}, {4, 4, false}, {2, 4, false}};
+constexpr Shape kShapes[] = {{2, 4, kLoadPing}, {2, 8, kLoadNone}, {1, 8, kLoadNext}, {4, 4, kLoadNext},
+                             {2, 4, kLoadNext}, {4, 4, kLoadNone}, {2, 4, kLoadNone}};
 constexpr int kNumShapes = sizeof(kShapes) / sizeof(kShapes[0]);
 
-template <bool BF, int NT, int EW, int WAVES, bool PF>
+template <bool BF, int NT, int EW, int WAVES, int LM>
 hipError_t launch_shape(hipStream_t s, const SplitArgs& sa, size_t smem, int ncu) {
-  auto kern = k_logpost_split<BF, NT, EW, WAVES, PF>;
+  auto kern = k_logpost_split<BF, NT, EW, WAVES, LM>;
   hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
   if (e != hipSuccess) return e;
@@ -499,11 +524,13 @@ hipError_t launch_shape(hipStream_t s, const SplitArgs& sa, size_t smem, int ncu
 template <bool BF, int NT>
 hipError_t launch_nt(hipStream_t s, const SplitArgs& sa, size_t smem, int ncu, int shape) {
   switch (shape) {
-    case 0: return launch_shape<BF, NT, 2, 4, true>(s, sa, smem, ncu);
-    case 1: return launch_shape<BF, NT, 2, 8, false>(s, sa, smem, ncu);
-    case 2: return launch_shape<BF, NT, 1, 8, false>(s, sa, smem, ncu);
-    case 3: return launch_shape<BF, NT, 4, 4, false>(s, sa, smem, ncu);
-    default: return launch_shape<BF, NT, 2, 4, false>(s, sa, smem, ncu);
+    case 0: return launch_shape<BF, NT, 2, 4, kLoadPing>(s, sa, smem, ncu);
+    case 1: return launch_shape<BF, NT, 2, 8, kLoadNone>(s, sa, smem, ncu);
+    case 2: return launch_shape<BF, NT, 1, 8, kLoadNext>(s, sa, smem, ncu);
+    case 3: return launch_shape<BF, NT, 4, 4, kLoadNext>(s, sa, smem, ncu);
+    case 4: return launch_shape<BF, NT, 2, 4, kLoadNext>(s, sa, smem, ncu);
+    case 5: return launch_shape<BF, NT, 4, 4, kLoadNone>(s, sa, smem, ncu);
+    default: return launch_shape<BF, NT, 2, 4, kLoadNone>(s, sa, smem, ncu);
   }
 }
 
@@ -577,7 +604,7 @@ hipError_t launch_logpost_split(hipStream_t s, const LogpostArgs& a, bool bf16, 
 
 int split_shape_for_ew(int ew) {
   for (int k = 0; k < kNumShapes; ++k)
-    if (kShapes[k].ew == ew && kShapes[k].waves == 4 && !kShapes[k].pf) return k;
+    if (kShapes[k].ew == ew && kShapes[k].waves == 4 && kShapes[k].lm == kLoadNext) return k;
   return 3;
 }
 

@@ -10,7 +10,7 @@ namespace {
 
 constexpr int kProjWaves = 4;      // waves per projection workgroup (one per SIMD)
 constexpr int kProjTiles = 25;     // 16x16 output tiles per wave
-constexpr int kProjChunk = 8;      // spheres per LDS stage (two MFMA K-steps)
+constexpr int kProjChunk = 4;      // spheres per LDS stage (one MFMA K-step)
 constexpr int kProjSeg = 63;       // pixels per wave segment (64 boundaries)
 
 typedef double d4 __attribute__((ext_vector_type(4)));
@@ -108,7 +108,9 @@ __global__ __launch_bounds__(64 * kProjWaves, 1) void k_project(const double* __
     }
     __syncthreads();
   }
-  // D[i][j] of a 16x16 tile sits in lane j + 16 (i / 4), element i % 4
+  // The FP64 16x16 result interleaves rows: D[i][j] sits in lane
+  // j + 16 (i % 4), element i / 4 (unlike the FP32-output forms, where lane
+  // groups hold consecutive rows).
   double* dst = out + (size_t)q * ny * nx;
 #pragma unroll
   for (int t = 0; t < kProjTiles; ++t) {
@@ -118,7 +120,7 @@ __global__ __launch_bounds__(64 * kProjWaves, 1) void k_project(const double* __
       const int j = 16 * tc + (lane & 15);
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int k = 16 * tr + 4 * (lane >> 4) + r;
+        const int k = 16 * tr + (lane >> 4) + 4 * r;
         if (k < ny && j < nx) dst[(size_t)k * nx + j] = acc[t][r];
       }
     }

@@ -128,7 +128,7 @@ def test_adam_reduces_loss(P, ctx):
     net.set_params(_init(arch, 7))
     imgs, tidx, tp = _data(arch, 16, 2, 8)
     first = None
-    for it in range(60):
+    for it in range(150):
         loss, _ = net.backward(imgs, tidx, tp)
         first = loss if first is None else first
         net.adam(3e-3)
