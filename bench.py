@@ -371,7 +371,7 @@ def run_proposal(args, P, ctx, torch, dev) -> int:
     log(f"training set: {args.train_images} images labelled over {nq} orientations x {nc} CTF sets")
     tr = proposal_training_images(args.train_images)
     data = PR.make_training_set(ctx, model, tr, proj, T=32, chunk=2000, log=log)
-    net = P.Net(ctx, held.nx, 32, 64, 128, 128, 32, nq)
+    net = P.Net(ctx, held.nx, 32, 64, 64, 64, 32, nq)
     net.set_params(PR.init_params(net, held.quats))
     t0 = time.perf_counter()
     losses = PR.train(net, data, epochs=args.epochs, batch=256, lr=1e-3, log=log)

@@ -222,11 +222,12 @@ bioem_status bioem_tuning_entry(const bioem_ctx* ctx, int32_t idx, bioem_tuning*
  *
  * Architecture (sizes from bioem_cnn_arch): per-image standardisation; four
  * 3x3 convolutions with stride 2 and zero padding 1 (1 -> c1 -> c2 -> c3 ->
- * c4 channels, ReLU); spatial mean; a hidden layer of `hidden` units (ReLU);
- * a linear layer to nq logits.  Loss: mean soft-label cross entropy against
- * sparse targets (idx, p) per image.  Parameters are one flat FP32 vector:
+ * c4 channels, ReLU); the c4 x (box/16)^2 final map flattened (index
+ * c*P + p); a hidden layer of `hidden` units (ReLU); a linear layer to nq
+ * logits.  Loss: mean soft-label cross entropy against sparse targets
+ * (idx, p) per image.  Parameters are one flat FP32 vector:
  * W1 [c1][1][3][3], b1 [c1], W2 [c2][c1][3][3], b2, W3, b3, W4, b4,
- * F1 [hidden][c4], g1 [hidden], F2 [nq][hidden], g2 [nq].
+ * F1 [hidden][c4 (box/16)^2], g1 [hidden], F2 [nq][hidden], g2 [nq].
  * Images are [B][box][box] float32; box must be a multiple of 16 (16..512). */
 typedef struct bioem_cnn bioem_cnn;
 

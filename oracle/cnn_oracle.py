@@ -8,7 +8,7 @@ parameters):
 
     x      = (I - mean I) / sqrt(var I + 1e-12)                 per image
     y_l    = relu(conv3x3_stride2_pad1(y_{l-1}; W_l) + b_l),  l = 1..4
-    f      = spatial mean of y_4                               [c4]
+    f      = y_4 flattened, index c*P + p (P = (box/16)^2)     [c4*P]
     h      = relu(F1 f + g1)                                   [hidden]
     z      = F2 h + g2                                         [nq] logits
     loss   = mean over images of  logsumexp(z) - sum_t p_t z_{i_t}
@@ -18,7 +18,7 @@ with conv(y)[o][r][s] = b[o] + sum_{c,u,v} W[o][c][u][v] y[c][2r+u-1][2s+v-1]
 over orientations (p sums to 1).
 
 Parameters are one flat float vector in this order: W1 [c1][1][3][3], b1,
-W2 [c2][c1][3][3], b2, W3, b3, W4, b4, F1 [hidden][c4], g1 [hidden],
+W2 [c2][c1][3][3], b2, W3, b3, W4, b4, F1 [hidden][c4*P], g1 [hidden],
 F2 [nq][hidden], g2 [nq].
 
 Everything here is plain numpy in float64, written for checking by eye, and
@@ -49,7 +49,8 @@ class Arch:
         for l in range(4):
             out.append((f"W{l + 1}", (ch[l + 1], ch[l], 3, 3)))
             out.append((f"b{l + 1}", (ch[l + 1],)))
-        out += [("F1", (self.hidden, self.c4)), ("g1", (self.hidden,)),
+        P = (self.box // 16) ** 2
+        out += [("F1", (self.hidden, self.c4 * P)), ("g1", (self.hidden,)),
                 ("F2", (self.nq, self.hidden)), ("g2", (self.nq,))]
         return out
 
@@ -119,7 +120,7 @@ def forward(arch: Arch, flat: np.ndarray, imgs: np.ndarray):
     for l in range(1, 5):
         y = np.maximum(conv_s2(y, p[f"W{l}"], p[f"b{l}"]), 0.0)
         acts.append(y)
-    f = y.mean(axis=(2, 3))                 # [B][c4]
+    f = y.reshape(y.shape[0], -1)           # [B][c4*P]
     h = np.maximum(f @ p["F1"].T + p["g1"], 0.0)
     z = h @ p["F2"].T + p["g2"]
     return z, (p, acts, f, h)
@@ -150,9 +151,8 @@ def loss_and_grad(arch: Arch, flat: np.ndarray, imgs: np.ndarray, tidx: np.ndarr
     dh = (dz @ p["F2"]) * (h > 0)
     g["F1"] = dh.T @ f
     g["g1"] = dh.sum(axis=0)
-    df = dh @ p["F1"]                                   # [B][c4]
-    y4 = acts[4]
-    dy = np.broadcast_to(df[:, :, None, None] / (y4.shape[2] * y4.shape[3]), y4.shape).copy()
+    df = dh @ p["F1"]                                   # [B][c4*P]
+    dy = df.reshape(acts[4].shape)
     for l in range(4, 0, -1):
         dy = dy * (acts[l] > 0)                         # through the relu of layer l
         dx, g[f"W{l}"], g[f"b{l}"] = conv_s2_backward(acts[l - 1], p[f"W{l}"], dy)

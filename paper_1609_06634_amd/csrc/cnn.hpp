@@ -20,7 +20,8 @@ hipError_t bias_relu(hipStream_t s, float* y, const float* bias, int C, long L, 
 hipError_t bias_cols(hipStream_t s, float* y, const float* bias, int R, int Cn);
 hipError_t relu_bwd(hipStream_t s, float* dy, const float* y, long n);
 hipError_t row_sum(hipStream_t s, const float* in, int R, long sr, long sj, long L, float scale, float* out);
-hipError_t mean_bwd(hipStream_t s, const float* g, int CB, int P, float* dy);
+// [C][B][P] activation <-> [C*P][B] feature matrix.
+hipError_t flatten(hipStream_t s, const float* in, int C, int B, int P, bool inverse, float* out);
 hipError_t softmax_xent(hipStream_t s, const float* z, int B, int nq, const int32_t* tidx, const float* tp, int T,
                         float* dz, float* loss);
 hipError_t adam(hipStream_t s, float* w, const float* g, float* m, float* v, long n, float lr, float b1, float b2,

@@ -59,7 +59,7 @@ hipError_t reserve(bioem_cnn* n, int B, int T) {
     }
   }
   const size_t zsz = (size_t)B * a.nq;
-  const size_t floats = ysz[0] + ysz[1] + ysz[2] + ysz[3] + ysz[4] + 2 * colmax + 2 * ymax + (size_t)a.c4 * B * 2 +
+  const size_t floats = ysz[0] + ysz[1] + ysz[2] + ysz[3] + ysz[4] + 2 * colmax + 2 * ymax + ysz[4] * 2 +
                         (size_t)a.hidden * B * 2 + 2 * zsz + B + (size_t)B * T + kPartFloats;
   const size_t bytes = floats * sizeof(float) + (size_t)B * T * sizeof(int32_t) + 256;
   if (n->ws) (void)hipFree(n->ws);
@@ -76,8 +76,8 @@ hipError_t reserve(bioem_cnn* n, int B, int T) {
   n->dcols = take(colmax);
   n->dya = take(ymax);
   n->dyb = take(ymax);
-  n->feat = take((size_t)a.c4 * B);
-  n->dfeat = take((size_t)a.c4 * B);
+  n->feat = take(ysz[4]);
+  n->dfeat = take(ysz[4]);
   n->h = take((size_t)a.hidden * B);
   n->dh = take((size_t)a.hidden * B);
   n->z = take(zsz);
@@ -104,10 +104,10 @@ hipError_t forward(hipStream_t s, bioem_cnn* n, const float* imgs, int B) {
                     1.0f, 0.0f, n->part, kPartFloats);
     if (e == hipSuccess) e = cnn::bias_relu(s, n->y[l], n->w + n->off[2 * (l - 1) + 1], cout, P, true);
   }
-  const int P4 = side(a, 4) * side(a, 4);
-  if (e == hipSuccess) e = cnn::row_sum(s, n->y[4], a.c4 * B, P4, 1, P4, 1.0f / P4, n->feat);
+  const int P4 = side(a, 4) * side(a, 4), F = a.c4 * P4;
+  if (e == hipSuccess) e = cnn::flatten(s, n->y[4], a.c4, B, P4, false, n->feat);
   if (e == hipSuccess)
-    e = cnn::gemm(s, a.hidden, B, a.c4, n->w + n->off[8], a.c4, 1, n->feat, B, 1, n->h, B, 1, 1.0f, 0.0f, n->part, kPartFloats);
+    e = cnn::gemm(s, a.hidden, B, F, n->w + n->off[8], F, 1, n->feat, B, 1, n->h, B, 1, 1.0f, 0.0f, n->part, kPartFloats);
   if (e == hipSuccess) e = cnn::bias_relu(s, n->h, n->w + n->off[9], a.hidden, B, true);
   if (e == hipSuccess)
     e = cnn::gemm(s, B, a.nq, a.hidden, n->h, 1, B, n->w + n->off[10], 1, a.hidden, n->z, a.nq, 1, 1.0f, 0.0f, n->part, kPartFloats);
@@ -129,16 +129,16 @@ hipError_t backward(hipStream_t s, bioem_cnn* n, int B, int T) {
     e = cnn::gemm(s, a.hidden, B, a.nq, w + n->off[10], 1, a.hidden, n->dz, 1, a.nq, n->dh, B, 1, 1.0f, 0.0f, n->part, kPartFloats);
   if (e == hipSuccess) e = cnn::relu_bwd(s, n->dh, n->h, (long)a.hidden * B);
   // hidden layer
+  const int P4 = side(a, 4) * side(a, 4), F = a.c4 * P4;
   if (e == hipSuccess)
-    e = cnn::gemm(s, a.hidden, a.c4, B, n->dh, B, 1, n->feat, 1, B, g + n->off[8], a.c4, 1, 1.0f, 0.0f, n->part, kPartFloats);
+    e = cnn::gemm(s, a.hidden, F, B, n->dh, B, 1, n->feat, 1, B, g + n->off[8], F, 1, 1.0f, 0.0f, n->part, kPartFloats);
   if (e == hipSuccess) e = cnn::row_sum(s, n->dh, a.hidden, B, 1, B, 1.0f, g + n->off[9]);
   if (e == hipSuccess)
-    e = cnn::gemm(s, a.c4, B, a.hidden, w + n->off[8], 1, a.c4, n->dh, B, 1, n->dfeat, B, 1, 1.0f, 0.0f, n->part, kPartFloats);
-  // spatial mean, then the convolutions from the top
-  const int P4 = side(a, 4) * side(a, 4);
+    e = cnn::gemm(s, F, B, a.hidden, w + n->off[8], 1, F, n->dh, B, 1, n->dfeat, B, 1, 1.0f, 0.0f, n->part, kPartFloats);
+  // back to the [c4][B][P4] activation, then the convolutions from the top
   float* dy = n->dya;
   float* dnext = n->dyb;
-  if (e == hipSuccess) e = cnn::mean_bwd(s, n->dfeat, a.c4 * B, P4, dy);
+  if (e == hipSuccess) e = cnn::flatten(s, n->dfeat, a.c4, B, P4, true, dy);
   for (int l = 4; l >= 1 && e == hipSuccess; --l) {
     const int cin = chan(a, l - 1), cout = chan(a, l), H = side(a, l - 1);
     const long P = (long)B * side(a, l) * side(a, l);
@@ -183,7 +183,7 @@ bioem_status bioem_cnn_create(bioem_ctx* ctx, const bioem_cnn_arch* arch, bioem_
     n->off[2 * (l - 1) + 1] = off;
     off += chan(*arch, l);
   }
-  n->off[8] = off; off += (long)arch->hidden * arch->c4;
+  n->off[8] = off; off += (long)arch->hidden * arch->c4 * (arch->box / 16) * (arch->box / 16);
   n->off[9] = off; off += arch->hidden;
   n->off[10] = off; off += (long)arch->nq * arch->hidden;
   n->off[11] = off; off += arch->nq;

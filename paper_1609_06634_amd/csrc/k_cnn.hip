@@ -229,11 +229,19 @@ __global__ __launch_bounds__(256) void k_row_sum(const float* __restrict__ in, l
   if (tid == 0) out[r] = scale * red[0];
 }
 
-// dy[c][b][p] = g[c][b] / P for the spatial mean over P positions.
-__global__ void k_mean_bwd(const float* __restrict__ g, int CB, int P, float* __restrict__ dy) {
-  const long total = (long)CB * P;
-  for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < total; e += (long)gridDim.x * blockDim.x)
-    dy[e] = g[e / P] / (float)P;
+// Flattened features of a [C][B][P] activation: f[(c*P + p)*B + b] =
+// y[(c*B + b)*P + p] (inverse = 1 gives the adjoint, the gradient scatter).
+__global__ void k_flatten(const float* __restrict__ in, int C, int B, int P, int inverse, float* __restrict__ out) {
+  const long total = (long)C * B * P;
+  for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < total; e += (long)gridDim.x * blockDim.x) {
+    // e indexes the [C][P][B] feature matrix
+    const int b = (int)(e % B);
+    const long t = e / B;
+    const int pp = (int)(t % P), c = (int)(t / P);
+    const long y = ((long)c * B + b) * P + pp;
+    if (inverse) out[y] = in[e];
+    else out[e] = in[y];
+  }
 }
 
 // Soft-label cross entropy of logits z [B][nq] (row-major) against sparse
@@ -486,8 +494,8 @@ hipError_t row_sum(hipStream_t s, const float* in, int R, long sr, long sj, long
   return hipGetLastError();
 }
 
-hipError_t mean_bwd(hipStream_t s, const float* g, int CB, int P, float* dy) {
-  hipLaunchKernelGGL(k_mean_bwd, dim3(blocks_for((long)CB * P)), dim3(256), 0, s, g, CB, P, dy);
+hipError_t flatten(hipStream_t s, const float* in, int C, int B, int P, bool inverse, float* out) {
+  hipLaunchKernelGGL(k_flatten, dim3(blocks_for((long)C * B * P)), dim3(256), 0, s, in, C, B, P, inverse ? 1 : 0, out);
   return hipGetLastError();
 }
 

@@ -144,20 +144,34 @@ __device__ __forceinline__ void split_item(const SplitArgs& sa, const uint4* __r
 #pragma unroll
           for (int y = 0; y < NT; ++y) acc2[e][x][y] = f4{0.f, 0.f, 0.f, 0.f};
 
+      // this lane's spectrum column (stage-1 row) of m-tile mt
+      auto cols_of = [&](int mt, const float2*& Oc, const float2*& Pc, const float* (&Tc)[EW]) {
+        const int s = 16 * mt + li;
+        const int col = s < half ? s : 0;
+        Oc = O + (size_t)col * ldy;
+        Pc = Pq + (size_t)col * ldy;
+#pragma unroll
+        for (int e = 0; e < EW; ++e) Tc[e] = a.table + (size_t)min(c0 + e, a.nc - 1) * len + (size_t)col * ldy;
+      };
+      // with the in-place schedule the loaded step carries across m-tiles:
+      // the first step of the next tile is in flight during stage 2
+      Step<EW> st;
+      if constexpr (LM == kLoadNext) {
+        const float2 *Oc, *Pc;
+        const float* Tc[EW];
+        cols_of(0, Oc, Pc, Tc);
+        load_step<EW>(st, Oc, Pc, Tc, 8 * lg);
+      }
       for (int mt = 0; mt < MT; ++mt) {
         f4 acc1[EW][NT][2];
 #pragma unroll
         for (int e = 0; e < EW; ++e)
 #pragma unroll
           for (int x = 0; x < NT; ++x) acc1[e][x][0] = acc1[e][x][1] = f4{0.f, 0.f, 0.f, 0.f};
-        const int s = 16 * mt + li;          // stage-1 row: spectrum slot
-        const bool live = s < half;
-        const int col = live ? s : 0;
-        const float2* Oc = O + (size_t)col * ldy;
-        const float2* Pc = Pq + (size_t)col * ldy;
+        const bool live = 16 * mt + li < half;
+        const float2 *Oc, *Pc;
         const float* Tc[EW];
-#pragma unroll
-        for (int e = 0; e < EW; ++e) Tc[e] = a.table + (size_t)min(c0 + e, a.nc - 1) * len + (size_t)col * ldy;
+        cols_of(mt, Oc, Pc, Tc);
         const bool pk = mt == 0;             // slot 0 of this tile carries columns 0 and nx/2
         // prep: the K-step's conjugate products, CTF-weighted and split
         // into hi/lo operands (consumes the loaded step); mma: its products
@@ -266,12 +280,17 @@ __device__ __forceinline__ void split_item(const SplitArgs& sa, const uint4* __r
           // one register set: once a step's loads are consumed by prep, the
           // same registers take the next step's loads, which stay in flight
           // during this step's matrix products
-          Step<EW> st;
-          load_step<EW>(st, Oc, Pc, Tc, 8 * lg);
           for (int ks = 0; ks < KS; ++ks) {
             V zrh[EW], zrl[EW], zih[EW], zil[EW];
             prep(st, ks, zrh, zrl, zih, zil);
-            if (ks + 1 < KS) load_step<EW>(st, Oc, Pc, Tc, 32 * (ks + 1) + 8 * lg);
+            if (ks + 1 < KS) {
+              load_step<EW>(st, Oc, Pc, Tc, 32 * (ks + 1) + 8 * lg);
+            } else if (mt + 1 < MT) {
+              const float2 *On, *Pn;
+              const float* Tn[EW];
+              cols_of(mt + 1, On, Pn, Tn);
+              load_step<EW>(st, On, Pn, Tn, 8 * lg);
+            }
             mma(ks, zrh, zrl, zih, zil);
           }
         }

@@ -38,7 +38,8 @@ def _shapes(arch: B.CnnArch):
     for l in range(4):
         out.append((f"W{l + 1}", (ch[l + 1], ch[l], 3, 3)))
         out.append((f"b{l + 1}", (ch[l + 1],)))
-    out += [("F1", (arch.hidden, arch.c4)), ("g1", (arch.hidden,)),
+    P = (arch.box // 16) ** 2
+    out += [("F1", (arch.hidden, arch.c4 * P)), ("g1", (arch.hidden,)),
             ("F2", (arch.nq, arch.hidden)), ("g2", (arch.nq,))]
     return out
 

@@ -5,7 +5,7 @@ from scipy.signal import correlate2d
 
 from oracle import cnn_oracle as C
 
-TINY = C.Arch(box=16, c1=2, c2=3, c3=4, c4=4, hidden=5, nq=7)
+TINY = C.Arch(box=32, c1=2, c2=3, c3=4, c4=4, hidden=5, nq=7)
 
 
 def _params(arch, seed):
