@@ -404,6 +404,9 @@ def run_proposal(args, P, ctx, torch, dev) -> int:
     ref = ref.cpu().numpy()
     d = ref - r.logp
     tex, tpr = float(np.mean(t_ex)), float(np.mean(t_pr))
+    # the proposal alone (no fallback): what the network's top-K captures
+    r0 = PR.score_with_proposal(ctx, net, proj, imgs, ctf, S, K=args.topk, tau=0.0, prec=args.prec)
+    d0 = ref - r0.logp
     line = {"metric": METRIC + " (effective, learned top-K proposal)", "value": evals / tpr,
             "unit": "evals/s", "n_gpus": 1, "steps": args.steps, "warmup": 1, "ms_per_step": tpr * 1e3,
             "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
@@ -418,6 +421,10 @@ def run_proposal(args, P, ctx, torch, dev) -> int:
             "dlogp": {"max": float(d.max()), "median": float(np.median(d)),
                       "frac_le_0.1": float(np.mean(d <= 0.1)), "min": float(d.min())},
             "fallback_fraction": float(r.fallback.mean()),
+            "pruned_only": {"dlogp_median": float(np.median(d0)), "frac_le_0.1": float(np.mean(d0 <= 0.1)),
+                            "random_topk_fraction_of_grid": args.topk / nq,
+                            "network_mass_median": float(np.median(r0.mass)),
+                            "ms_per_step": r0.seconds * 1e3},
             "evals_computed_fraction": r.evals / evals,
             "training": {"images": args.train_images, "epochs": args.epochs, "seconds": t_train,
                          "label_seconds": label_s, "loss_per_epoch": losses,

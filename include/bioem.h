@@ -110,8 +110,11 @@ typedef struct {
   int32_t reserved[4];     /* must be zero */
 } bioem_opts;
 
-/* Create a context on HIP device `device`.  `hip_stream` is a hipStream_t to
- * enqueue on, or NULL for a stream the context creates and owns. */
+/* Create a context on HIP device `device`.  `hip_stream` is the hipStream_t
+ * every call enqueues on; NULL means the device's null (legacy default)
+ * stream, so work that other code enqueues there (a framework's default
+ * stream) is ordered with the library's.  Inputs in device memory must be
+ * complete in the order of that stream when a call is made. */
 bioem_status bioem_create(int device, void* hip_stream, bioem_ctx** out);
 void bioem_destroy(bioem_ctx* ctx);
 const char* bioem_last_error(const bioem_ctx* ctx);
@@ -228,7 +231,8 @@ bioem_status bioem_tuning_entry(const bioem_ctx* ctx, int32_t idx, bioem_tuning*
  * (idx, p) per image.  Parameters are one flat FP32 vector:
  * W1 [c1][1][3][3], b1 [c1], W2 [c2][c1][3][3], b2, W3, b3, W4, b4,
  * F1 [hidden][c4 (box/16)^2], g1 [hidden], F2 [nq][hidden], g2 [nq].
- * Images are [B][box][box] float32; box must be a multiple of 16 (16..512). */
+ * Inputs are [B][box][box] float32 (normally bioem_cnn_input of the
+ * particle images); box must be a multiple of 16 (16..512). */
 typedef struct bioem_cnn bioem_cnn;
 
 typedef struct {
@@ -263,6 +267,15 @@ bioem_status bioem_cnn_adam(bioem_ctx* ctx, bioem_cnn* net, float lr, float beta
  * mass [B] float32 (NULL to skip); outputs per out_mem. */
 bioem_status bioem_cnn_propose(bioem_ctx* ctx, bioem_cnn* net, const float* imgs, int32_t B, int32_t in_mem,
                                int32_t K, int32_t* cand, float* mass, int32_t out_mem);
+
+/* The network's input for raw images: the circular autocorrelation of each
+ * mean-free image, re-centred so that lag 0 sits at pixel (ny/2, nx/2), with
+ * lag 0 itself set to 0 (it carries the noise power).  It does not change
+ * when the particle is shifted (circularly) within the box, so the network
+ * need not learn the in-plane displacement.  imgs [B][ny][nx] float32 ->
+ * out [B][ny][nx] float32 (FP64 transforms), memory per in_mem / out_mem. */
+bioem_status bioem_cnn_input(bioem_ctx* ctx, const float* imgs, int32_t B, int32_t nx, int32_t ny, int32_t in_mem,
+                             float* out, int32_t out_mem);
 
 /* Top-K of each row of z [B][n] float32 (host or device per in_mem): idx
  * [B][K] int32 in increasing index order (ties to the lower index) and the

@@ -6,7 +6,9 @@ itself produces (Section 3, Extra features: the posterior restricted to each
 orientation).  Architecture (fixed by the proposal design, sizes are
 parameters):
 
-    x      = (I - mean I) / sqrt(var I + 1e-12)                 per image
+    x      = (I - mean I) / sqrt(var I + 1e-12)                 per input
+             (the input is normally network_input(image): the image's
+             centred autocorrelation, which a shift does not change)
     y_l    = relu(conv3x3_stride2_pad1(y_{l-1}; W_l) + b_l),  l = 1..4
     f      = y_4 flattened, index c*P + p (P = (box/16)^2)     [c4*P]
     h      = relu(F1 f + g1)                                   [hidden]
@@ -70,6 +72,20 @@ def unflatten(arch: Arch, flat: np.ndarray) -> Dict[str, np.ndarray]:
 
 def flatten(arch: Arch, p: Dict[str, np.ndarray]) -> np.ndarray:
     return np.concatenate([p[name].ravel() for name, _ in arch.shapes()])
+
+
+def network_input(imgs: np.ndarray) -> np.ndarray:
+    """Circular autocorrelation of each mean-free image, lag 0 moved to pixel
+    (H/2, W/2) and set to 0: sum_x u(x) u(x + r) with u = I - mean(I)."""
+    x = np.asarray(imgs, dtype=np.float64)
+    u = x - x.mean(axis=(1, 2), keepdims=True)
+    H, W = u.shape[1:]
+    out = np.empty_like(u)
+    for b in range(u.shape[0]):
+        a = np.fft.irfft2(np.abs(np.fft.rfft2(u[b])) ** 2, s=(H, W))
+        a[0, 0] = 0.0
+        out[b] = np.roll(a, (H // 2, W // 2), axis=(0, 1))
+    return out
 
 
 def standardize(imgs: np.ndarray) -> np.ndarray:

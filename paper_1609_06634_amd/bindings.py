@@ -106,6 +106,7 @@ SIGNATURES = [
     ("bioem_cnn_adam", _I, [_P, _P, ctypes.c_float, ctypes.c_float, ctypes.c_float, ctypes.c_float]),
     ("bioem_cnn_propose", _I, [_P, _P, _P, _I, _I, _I, _P, _P, _I]),
     ("bioem_topk", _I, [_P, _P, _I, _I, _I, _I, _P, _P, _I]),
+    ("bioem_cnn_input", _I, [_P, _P, _I, _I, _I, _I, _P, _I]),
 ]
 
 
@@ -163,14 +164,16 @@ def _arg(x, dtype, shape=None):
 
 class Context:
     """A library context on one device, enqueuing on torch's current stream
-    (or on a stream of its own when ``own_stream`` is set)."""
+    (or on a new torch stream when ``own_stream`` is set)."""
 
     def __init__(self, device: int = 0, own_stream: bool = False):
         self._lib = load()
-        stream = None
-        if not own_stream:
-            torch = _torch()
-            stream = torch.cuda.current_stream(device).cuda_stream
+        torch = _torch()
+        # the library enqueues on torch's current stream (or a new torch
+        # stream), so torch ops on the tensors it reads or writes are ordered
+        # with its kernels; handle 0 is the null stream
+        self._stream = torch.cuda.Stream(device) if own_stream else torch.cuda.current_stream(device)
+        stream = self._stream.cuda_stream or None
         h = ctypes.c_void_p()
         st = self._lib.bioem_create(device, stream, ctypes.byref(h))
         if st != BIOEM_OK:
@@ -334,6 +337,20 @@ def logpost_batch(ctx: Context, jobs, prec: str = "split_f16", mode: str = "pers
     ctx.check(ctx._lib.bioem_logpost_batch(ctx.h, arr, len(jobs), PREC[prec],
                                            MEM_DEVICE if device_out else MEM_HOST, m))
     return outs
+
+
+def cnn_input(ctx: Context, imgs, device_out: bool = False):
+    """Centred autocorrelation of each mean-free image (the network input)."""
+    ip, m, keep = _arg(imgs, np.float32)
+    B, ny, nx = (int(v) for v in keep.shape)
+    if device_out:
+        torch = _torch()
+        out = torch.empty((B, ny, nx), dtype=torch.float32, device=torch.device("cuda", ctx.device))
+        ctx.check(ctx._lib.bioem_cnn_input(ctx.h, ip, B, nx, ny, m, out.data_ptr(), MEM_DEVICE))
+        return out
+    out = np.empty((B, ny, nx), np.float32)
+    ctx.check(ctx._lib.bioem_cnn_input(ctx.h, ip, B, nx, ny, m, out.ctypes.data, MEM_HOST))
+    return out
 
 
 def topk(ctx: Context, z, K: int, device_out: bool = False):

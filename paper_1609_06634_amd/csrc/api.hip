@@ -374,15 +374,9 @@ bioem_status bioem_create(int device, void* hip_stream, bioem_ctx** out) {
   if (!ctx) return BIOEM_ENOMEM;
   ctx->device = device;
   if (hipSetDevice(device) != hipSuccess) { delete ctx; return BIOEM_EDEVICE; }
-  if (hip_stream) {
-    ctx->stream = static_cast<hipStream_t>(hip_stream);
-  } else {
-    if (hipStreamCreateWithFlags(&ctx->stream, hipStreamNonBlocking) != hipSuccess) {
-      delete ctx;
-      return BIOEM_EDEVICE;
-    }
-    ctx->own_stream = true;
-  }
+  // NULL is the device's null (legacy default) stream, which other users of
+  // that stream (e.g. a framework's default stream) are ordered with
+  ctx->stream = static_cast<hipStream_t>(hip_stream);
   *out = ctx;
   return BIOEM_OK;
 }
@@ -392,10 +386,7 @@ void bioem_destroy(bioem_ctx* ctx) {
   (void)hipSetDevice(ctx->device);
   for (auto e : ctx->ev_start) (void)hipEventDestroy(e);
   for (auto e : ctx->ev_stop) (void)hipEventDestroy(e);
-  if (ctx->own_stream && ctx->stream) {
-    (void)hipStreamSynchronize(ctx->stream);
-    (void)hipStreamDestroy(ctx->stream);
-  }
+  (void)hipStreamSynchronize(ctx->stream);
   delete ctx;
 }
 

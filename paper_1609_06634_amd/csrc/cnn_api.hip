@@ -369,6 +369,40 @@ bioem_status bioem_cnn_propose(bioem_ctx* ctx, bioem_cnn* n, const float* imgs, 
   return BIOEM_OK;
 }
 
+bioem_status bioem_cnn_input(bioem_ctx* ctx, const float* imgs, int32_t B, int32_t nx, int32_t ny, int32_t in_mem,
+                             float* out, int32_t out_mem) {
+  if (!ctx) return BIOEM_EINVAL;
+  if (!imgs || !out || B < 1 || nx < 4 || ny < 4 || nx > kMaxBox || ny > kMaxBox || nx % 2 || ny % 2 ||
+      !valid_mem(in_mem) || !valid_mem(out_mem))
+    return fail(ctx, BIOEM_EINVAL, "bioem_cnn_input: bad argument");
+  HIP_OR_FAIL(ctx, hipSetDevice(ctx->device));
+  hipStream_t s = ctx->stream;
+  const int bb = std::min<int>(B, kMaxBatch), mh = nx / 2 + 1;
+  const size_t npix = (size_t)nx * ny, nspec = (size_t)mh * ny;
+  DevMem scratch, stage_in, stage_out;
+  HIP_OR_FAIL(ctx, scratch.alloc((sizeof(double2) * 3 * nspec + sizeof(double) * npix) * bb));
+  double2* rows = scratch.as<double2>();
+  double2* spec = rows + nspec * bb;
+  double2* cols = spec + nspec * bb;
+  double* a64 = reinterpret_cast<double*>(cols + nspec * bb);
+  if (in_mem == BIOEM_MEM_HOST) HIP_OR_FAIL(ctx, stage_in.alloc(sizeof(float) * npix * bb));
+  if (out_mem == BIOEM_MEM_HOST) HIP_OR_FAIL(ctx, stage_out.alloc(sizeof(float) * npix * bb));
+  for (int b0 = 0; b0 < B; b0 += bb) {
+    const int cb = std::min(bb, B - b0);
+    const float* src = imgs + npix * b0;
+    if (in_mem == BIOEM_MEM_HOST) {
+      HIP_OR_FAIL(ctx, hipMemcpyAsync(stage_in.p, src, sizeof(float) * npix * cb, hipMemcpyHostToDevice, s));
+      src = stage_in.as<float>();
+    }
+    float* dst = out_mem == BIOEM_MEM_HOST ? stage_out.as<float>() : out + npix * b0;
+    HIP_OR_FAIL(ctx, launch_autocorr(s, src, cb, nx, ny, rows, spec, cols, a64, dst));
+    if (out_mem == BIOEM_MEM_HOST)
+      HIP_OR_FAIL(ctx, hipMemcpyAsync(out + npix * b0, dst, sizeof(float) * npix * cb, hipMemcpyDeviceToHost, s));
+  }
+  HIP_OR_FAIL(ctx, hipStreamSynchronize(s));
+  return BIOEM_OK;
+}
+
 bioem_status bioem_topk(bioem_ctx* ctx, const float* z, int32_t B, int32_t n, int32_t K, int32_t in_mem,
                         int32_t* idx, float* mass, int32_t out_mem) {
   if (!ctx) return BIOEM_EINVAL;

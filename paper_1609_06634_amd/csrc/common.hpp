@@ -12,8 +12,7 @@
 
 struct bioem_ctx {
   int device = 0;
-  hipStream_t stream = nullptr;
-  bool own_stream = false;
+  hipStream_t stream = nullptr;   // the caller's stream (nullptr: the null stream)
   std::string err;
   // optional timing of the main kernel launches of the last bioem_logpost
   bool timing = false;
@@ -76,6 +75,13 @@ hipError_t launch_render(hipStream_t s, const float2* spec, const int32_t* expo,
                          int ny, double pixel, const double* ctf, const int32_t* shifts,
                          const double* norm_offset, const float* noise, double snr,
                          double2* spec64, double2* cols_scratch, double* i1, float* out);
+
+// Centred circular autocorrelation of mean-free images (lag 0 zeroed), the
+// proposal network's shift-invariant input: imgs [n][ny][nx] float ->
+// out [n][ny][nx] float; scratch rows/spec/cols [n][nx/2+1][ny] double2,
+// a64 [n][ny][nx] double.
+hipError_t launch_autocorr(hipStream_t s, const float* imgs, int n, int nx, int ny, double2* rows_scratch,
+                           double2* spec64, double2* cols_scratch, double* a64, float* out);
 
 // Likelihood support.
 hipError_t launch_ctf_table(hipStream_t s, const double* ctf, int nc, int nx, int ny, double pixel,

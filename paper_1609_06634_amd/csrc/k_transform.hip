@@ -2,6 +2,8 @@
 // synthetic maps.  None of this is on the per-evaluation hot loop (it runs
 // once per orientation or per image, Listing 1's outer loops), so it favours
 // accuracy: every step computes in FP64 and only the stored spectra are FP32.
+#include <algorithm>
+
 #include "common.hpp"
 
 namespace bioem {
@@ -401,6 +403,30 @@ __global__ __launch_bounds__(256) void k_proj_norms(const float2* __restrict__ p
   if (threadIdx.x == 0) B[blockIdx.x] = ldexp(s, 2 * pexpo[q]) / ((double)nx * ny);
 }
 
+// |X|^2 of a half spectrum [n][mh][ny] in place, with the DC term set to 0
+// (the image mean removed).
+__global__ void k_power(double2* __restrict__ spec, long total, int per_item) {
+  for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < total; e += (long)gridDim.x * blockDim.x) {
+    const double2 v = spec[e];
+    spec[e] = make_double2(e % per_item == 0 ? 0.0 : v.x * v.x + v.y * v.y, 0.0);
+  }
+}
+
+// Circular autocorrelation a[n][ny][nx] re-centred (lag 0 at (ny/2, nx/2),
+// i.e. out(y, x) = a((y + ny/2) mod ny, (x + nx/2) mod nx)) with lag 0 set to
+// 0 (it carries the noise power), as float.
+__global__ void k_ac_finish(const double* __restrict__ a, int n, int nx, int ny, float* __restrict__ out) {
+  const long total = (long)n * nx * ny;
+  for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < total; e += (long)gridDim.x * blockDim.x) {
+    const int x = (int)(e % nx);
+    const long t = e / nx;
+    const int y = (int)(t % ny);
+    const long b = t / ny;
+    const int ys = (y + ny / 2) % ny, xs = (x + nx / 2) % nx;
+    out[e] = (ys == 0 && xs == 0) ? 0.0f : (float)a[(b * ny + ys) * nx + xs];
+  }
+}
+
 }  // namespace
 
 static hipError_t last() { return hipGetLastError(); }
@@ -443,6 +469,22 @@ hipError_t launch_render(hipStream_t s, const float2* spec, const int32_t* expo,
   hipLaunchKernelGGL(k_icrdft_rows, dim3(n * ny), dim3(128), 0, s, cols_scratch, nx, ny, i1);
   hipLaunchKernelGGL(k_render_finish, dim3(n), dim3(256), 0, s, i1, nx, ny, shifts, norm_offset,
                      noise, snr, out);
+  return last();
+}
+
+hipError_t launch_autocorr(hipStream_t s, const float* imgs, int n, int nx, int ny, double2* rows_scratch,
+                           double2* spec64, double2* cols_scratch, double* a64, float* out) {
+  const int mh = nx / 2 + 1;
+  const long total = (long)n * mh * ny;
+  hipError_t e = launch_rdft2(s, nullptr, imgs, n, nx, ny, rows_scratch, spec64);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_power, dim3((unsigned)std::min<long>((total + 255) / 256, 65536L)), dim3(256), 0, s, spec64,
+                     total, mh * ny);
+  hipLaunchKernelGGL(k_icdft_cols, dim3(n * mh), dim3(128), 0, s, spec64, nx, ny, cols_scratch);
+  hipLaunchKernelGGL(k_icrdft_rows, dim3(n * ny), dim3(128), 0, s, cols_scratch, nx, ny, a64);
+  const long pix = (long)n * nx * ny;
+  hipLaunchKernelGGL(k_ac_finish, dim3((unsigned)std::min<long>((pix + 255) / 256, 65536L)), dim3(256), 0, s, a64,
+                     n, nx, ny, out);
   return last();
 }
 

@@ -71,7 +71,7 @@ def init_params(net: B.Net, quats: np.ndarray, seed: int = 0, scale: float = 1.0
 
 @dataclass
 class TrainingSet:
-    images: "object"          # torch CUDA tensor [n][box][box] float32
+    inputs: "object"          # torch CUDA tensor [n][box][box] float32: network inputs
     tidx: np.ndarray          # [n][T] int32
     tp: np.ndarray            # [n][T] float32
     mass: np.ndarray          # [n] posterior mass of the T targets
@@ -91,24 +91,50 @@ def render_class_images(ctx: B.Context, model_dev, cls, i0: int, i1: int):
     return out
 
 
+def smooth_targets(quats: np.ndarray, top: np.ndarray, T: int, sigma_deg: float):
+    """Soft targets around each image's most probable orientation: the T grid
+    orientations nearest to it (rotation angle 2 arccos|q.q'|) with weights
+    exp(-angle^2 / (2 sigma^2)), normalised.  A training choice: the
+    posteriors themselves are nearly one-hot at these signal levels, and a
+    spread target gives neighbouring orientations a consistent gradient."""
+    q = np.asarray(quats, np.float64)
+    idx = np.empty((len(top), T), np.int32)
+    p = np.empty((len(top), T), np.float32)
+    s = np.deg2rad(sigma_deg)
+    for i0 in range(0, len(top), 512):
+        t = top[i0:i0 + 512]
+        dots = np.abs(q[t] @ q.T).clip(0.0, 1.0)
+        part = np.argpartition(-dots, T - 1, axis=1)[:, :T]
+        ang = 2.0 * np.arccos(np.take_along_axis(dots, part, axis=1))
+        w = np.exp(-ang ** 2 / (2 * s * s))
+        idx[i0:i0 + 512] = part
+        p[i0:i0 + 512] = w / w.sum(axis=1, keepdims=True)
+    return idx, p
+
+
 def make_training_set(ctx: B.Context, model: np.ndarray, cls, proj_grid: B.Projections, T: int = 32,
-                      chunk: int = 1000, prec: str = "split_f16", log=None) -> TrainingSet:
-    """Render the class's images and label each with its T most probable
-    orientations under the exhaustive posterior (renormalised over the T)."""
+                      chunk: int = 1000, prec: str = "split_f16", smooth_deg: float = 0.0,
+                      log=None) -> TrainingSet:
+    """Render the class's images, keep their network inputs (``cnn_input``)
+    and label each with its T most probable orientations under the
+    exhaustive posterior (renormalised over the T), or, with smooth_deg > 0,
+    with soft targets around its most probable orientation
+    (``smooth_targets``)."""
     import torch
     dev = torch.device("cuda", ctx.device)
     t0 = time.perf_counter()
     model_dev = torch.from_numpy(model).to(dev)
     ctf = torch.from_numpy(cls.ctf).to(dev)
     n = cls.n_images
-    images = torch.empty((n, cls.ny, cls.nx), dtype=torch.float32, device=dev)
+    inputs = torch.empty((n, cls.ny, cls.nx), dtype=torch.float32, device=dev)
     tidx = np.empty((n, T), np.int32)
     tp = np.empty((n, T), np.float32)
     mass = np.empty(n, np.float32)
     for i0 in range(0, n, chunk):
         i1 = min(n, i0 + chunk)
-        images[i0:i1] = render_class_images(ctx, model_dev, cls, i0, i1)
-        im = B.prepare_images(ctx, images[i0:i1])
+        imgs = render_class_images(ctx, model_dev, cls, i0, i1)
+        inputs[i0:i1] = B.cnn_input(ctx, imgs, device_out=True)
+        im = B.prepare_images(ctx, imgs)
         out = B.logpost(ctx, proj_grid, im, ctf, cls.max_shift, prec=prec, orient=True, device_out=True)
         im.free()
         lo = out["orient"].float()                  # log posterior per orientation
@@ -121,7 +147,10 @@ def make_training_set(ctx: B.Context, model: np.ndarray, cls, proj_grid: B.Proje
         if log:
             log(f"labels {i1}/{n} ({time.perf_counter() - t0:.0f} s)")
     torch.cuda.synchronize()
-    return TrainingSet(images=images, tidx=tidx, tp=tp, mass=mass, seconds=time.perf_counter() - t0)
+    if smooth_deg > 0.0:
+        best = tidx[np.arange(n), np.argmax(tp, axis=1)]
+        tidx, tp = smooth_targets(cls.quats, best, T, smooth_deg)
+    return TrainingSet(inputs=inputs, tidx=tidx, tp=tp, mass=mass, seconds=time.perf_counter() - t0)
 
 
 def train(net: B.Net, data: TrainingSet, epochs: int = 4, batch: int = 256, lr: float = 1e-3,
@@ -129,8 +158,8 @@ def train(net: B.Net, data: TrainingSet, epochs: int = 4, batch: int = 256, lr: 
     """Adam on shuffled mini-batches; returns the mean loss of every epoch."""
     import torch
     rng = np.random.default_rng(seed)
-    n = data.images.shape[0]
-    dev = data.images.device
+    n = data.inputs.shape[0]
+    dev = data.inputs.device
     tidx = torch.from_numpy(data.tidx).to(dev)
     tp = torch.from_numpy(data.tp).to(dev)
     losses = []
@@ -139,7 +168,7 @@ def train(net: B.Net, data: TrainingSet, epochs: int = 4, batch: int = 256, lr: 
         tot, cnt = 0.0, 0
         for b0 in range(0, n - batch + 1, batch):
             sel = torch.from_numpy(order[b0:b0 + batch]).to(dev)
-            loss, _ = net.backward(data.images[sel].contiguous(), tidx[sel].contiguous(), tp[sel].contiguous())
+            loss, _ = net.backward(data.inputs[sel].contiguous(), tidx[sel].contiguous(), tp[sel].contiguous())
             net.adam(lr)
             tot += loss
             cnt += 1
@@ -166,7 +195,7 @@ def score_with_proposal(ctx: B.Context, net: B.Net, proj_grid: B.Projections, im
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     nc = int(ctf.shape[0])
-    cand, mass = net.propose(images, K, device_out=True)
+    cand, mass = net.propose(B.cnn_input(ctx, images, device_out=True), K, device_out=True)
     im = B.prepare_images(ctx, images)
     out = B.logpost(ctx, proj_grid, im, ctf, max_shift, prec=prec, cand_q=cand, device_out=True)
     logp = out["logp"]

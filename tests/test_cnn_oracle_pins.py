@@ -76,3 +76,20 @@ def test_top_k_and_mass():
     full, m1 = C.top_k(z, 50)
     np.testing.assert_allclose(m1, 1.0, rtol=1e-15)
     assert np.all((mass > 0) & (mass < 1))
+
+
+def test_network_input_is_the_autocorrelation():
+    rng = np.random.default_rng(11)
+    img = rng.standard_normal((2, 8, 6))
+    got = C.network_input(img)
+    for b in range(2):
+        u = img[b] - img[b].mean()
+        for ry in range(8):
+            for rx in range(6):
+                ref = sum(u[y, x] * u[(y + ry) % 8, (x + rx) % 6] for y in range(8) for x in range(6))
+                if ry == 0 and rx == 0:
+                    ref = 0.0
+                assert abs(got[b, (ry + 4) % 8, (rx + 3) % 6] - ref) < 1e-12
+    # a circular shift of the particle leaves the input unchanged
+    shifted = np.roll(img, (3, -2), axis=(1, 2))
+    np.testing.assert_allclose(C.network_input(shifted), got, atol=1e-12)

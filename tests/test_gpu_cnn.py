@@ -151,6 +151,29 @@ def test_topk_matches_reference(P, ctx):
     net.close()
 
 
+def test_topk_reads_torch_output_in_stream_order(P, ctx):
+    """The library enqueues on torch's current stream, so a tensor that a
+    torch kernel has only just been asked to write is complete when the
+    library's kernels read it (top-K makes several passes over its input)."""
+    import torch
+    g = torch.Generator(device="cuda").manual_seed(5)
+    big = torch.randn((512, 36864), device="cuda", dtype=torch.float64, generator=g)
+    z = big.float()                                   # enqueued, not waited for
+    idx, mass = P.topk(ctx, z, 32, device_out=True)
+    vals = torch.gather(z, 1, idx.long())             # valid indices only
+    ref, _ = C.top_k(z.cpu().numpy().astype(np.float64), 32)
+    assert np.array_equal(idx.cpu().numpy(), ref)
+    assert vals.shape == (512, 32)
+
+
+def test_network_input_matches_reference(P, ctx):
+    rng = np.random.default_rng(12)
+    imgs = rng.standard_normal((5, 48, 40)).astype(np.float32) + 2.0
+    got = P.cnn_input(ctx, imgs)
+    ref = C.network_input(imgs)
+    assert np.abs(got - ref).max() < 1e-5 * np.abs(ref).max()
+
+
 def test_cnn_invalid_arguments(P, ctx):
     with pytest.raises(P.BioemError):
         P.Net(ctx, 40, 4, 4, 4, 4, 4, 10)          # box not a multiple of 16
