@@ -423,7 +423,7 @@ struct JobDesc {
   int block0;   // first work block of the job
 };
 
-template <bool BF, int WAVES>
+template <bool BF, int EW, int WAVES>
 __global__ __launch_bounds__(64 * WAVES, 1) void k_logpost_batch(const JobDesc* __restrict__ jobs, int njobs,
                                                                  int total_blocks) {
   extern __shared__ uint4 lds[];
@@ -441,13 +441,13 @@ __global__ __launch_bounds__(64 * WAVES, 1) void k_logpost_batch(const JobDesc* 
       cur = j;
     }
     const int item = (blk - jd.block0) * WAVES + (threadIdx.x >> 6);
-    switch (jd.nt * 8 + jd.ew) {   // uniform across the workgroup
-      case 1 * 8 + 2: split_item<BF, 1, 2, kLoadNone>(jd.sa, lds, lds + nF, item); break;
-      case 1 * 8 + 4: split_item<BF, 1, 4, kLoadNone>(jd.sa, lds, lds + nF, item); break;
-      case 2 * 8 + 2: split_item<BF, 2, 2, kLoadNone>(jd.sa, lds, lds + nF, item); break;
-      case 2 * 8 + 4: split_item<BF, 2, 4, kLoadNone>(jd.sa, lds, lds + nF, item); break;
-      case 3 * 8 + 2: split_item<BF, 3, 2, kLoadNone>(jd.sa, lds, lds + nF, item); break;
-      default: split_item<BF, 3, 4, kLoadNone>(jd.sa, lds, lds + nF, item); break;
+    // the bf16 split needs more registers: its three variants fit only
+    // with the plain load schedule
+    constexpr int LM = BF ? kLoadNone : kLoadNext;
+    switch (jd.nt) {   // uniform across the workgroup
+      case 1: split_item<BF, 1, EW, LM>(jd.sa, lds, lds + nF, item); break;
+      case 2: split_item<BF, 2, EW, LM>(jd.sa, lds, lds + nF, item); break;
+      default: split_item<BF, 3, EW, LM>(jd.sa, lds, lds + nF, item); break;
     }
   }
 }
@@ -629,6 +629,7 @@ int split_shape_for_ew(int ew) {
 
 hipError_t launch_logpost_batch(hipStream_t s, const BatchJob* jobs, int njobs, bool bf16) {
   constexpr int kWaves = 4;
+  constexpr int kBatchEW = 4;
   if (njobs < 1) return hipErrorInvalidValue;
   std::vector<JobDesc> desc(njobs);
   std::vector<uint4*> tabs(njobs, nullptr);
@@ -636,7 +637,7 @@ hipError_t launch_logpost_batch(hipStream_t s, const BatchJob* jobs, int njobs, 
   long blocks = 0;
   size_t smem = 0;
   for (int j = 0; j < njobs && e == hipSuccess; ++j) {
-    const int ew = jobs[j].ew == 2 ? 2 : 4;
+    const int ew = kBatchEW;   // one item width for the whole launch
     e = make_split_args(s, jobs[j].a, bf16, ew, jobs[j].ti, jobs[j].ts, desc[j].sa, tabs[j]);
     desc[j].nt = nt_for(jobs[j].a.S);
     desc[j].ew = ew;
@@ -652,7 +653,7 @@ hipError_t launch_logpost_batch(hipStream_t s, const BatchJob* jobs, int njobs, 
   if (e == hipSuccess)
     e = hipMemcpyAsync(djobs, desc.data(), sizeof(JobDesc) * njobs, hipMemcpyHostToDevice, s);
   if (e == hipSuccess) {
-    auto kern = bf16 ? k_logpost_batch<true, kWaves> : k_logpost_batch<false, kWaves>;
+    auto kern = bf16 ? k_logpost_batch<true, kBatchEW, kWaves> : k_logpost_batch<false, kBatchEW, kWaves>;
     e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern), hipFuncAttributeMaxDynamicSharedMemorySize,
                             (int)smem);
     if (e == hipSuccess) {
