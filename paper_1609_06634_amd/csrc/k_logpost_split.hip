@@ -30,8 +30,10 @@
 //   sum_d exp(l(d) - l_max) = sum_d (1 + u_d)^-(n/2-1),
 //   u_d = (rho^2_max - rho^2(d)) / (1 - rho^2_max) >= 0,
 // where every term lies in (0, 1] and the maximum term is exactly 1, so FP32
-// suffices.  When n/2-1 >= 1024, terms with u >= 0.05 are below e^-50 and
-// log1p(u) is a degree-5 series on [0, 0.05] (error below u^6/6).  Each
+// suffices.  When c = n/2-1 >= 1024, terms with u >= 0.05 are below e^-50
+// and log1p(u) is its degree-3 series on [0, 0.05]: the exponent error c u^4/4
+// changes a term t = e^{-c log1p(u)} by at most about t c u^4/4 <= 1.2 / c^3
+// (the product peaks at u = 4/c), below 2e-9 of the sum at c = 1024.  Each
 // evaluation leaves (max X^2, relative sum); the FP64 likelihood constants,
 // log-sum-exp merges and the best grid point are taken at finalisation, and
 // the best displacement of each image is recovered afterwards.
@@ -115,8 +117,8 @@ __device__ __forceinline__ void split_item(const SplitArgs& sa, const uint4* __r
   const bool ct_last_ok = (li & 7) <= S - 8 * (NT - 1);
   const bool ct0_ok = fr || (li & 7) != 0;
   const int lg4 = 4 * lg, wlast = W - 16 * (NT - 1);
-  // -(n/2-1) log2(e) times the series of log1p: u - u^2/2 + u^3/3 - u^4/4 + u^5/5
-  const float p1 = -c2l2e, p2 = 0.5f * c2l2e, p3 = -c2l2e / 3.0f, p4 = 0.25f * c2l2e, p5 = -0.2f * c2l2e;
+  // -(n/2-1) log2(e) times the series of log1p: u - u^2/2 + u^3/3
+  const float p1 = -c2l2e, p2 = 0.5f * c2l2e, p3 = -c2l2e / 3.0f;
 
   {
     const int tile = item / tile_items, rr = item - tile * tile_items;
@@ -380,7 +382,7 @@ __device__ __forceinline__ void split_item(const SplitArgs& sa, const uint4* __r
             const float x2 = acc2[e][k / (4 * NT)][(k / 4) % NT][k % 4];
             const float u = __builtin_amdgcn_fmed3f(fmaf(-x2, cu, base), 0.0f, 0.05f);
             // slots outside the window have u clamped to 0.05: below e^-50
-            sum += __builtin_amdgcn_exp2f(u * (p1 + u * (p2 + u * (p3 + u * (p4 + u * p5)))));
+            sum += __builtin_amdgcn_exp2f(u * (p1 + u * (p2 + u * p3)));
           }
         } else {
 #pragma unroll
