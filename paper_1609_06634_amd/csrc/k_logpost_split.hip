@@ -67,6 +67,7 @@ struct SplitArgs {
   int ncg;              // CTF groups per (image, orientation)
   int ti, ts;           // item tile: images x slots
   int n_ti, n_ts;       // item tiles along images and slots
+  int xcd;              // 1: tiles dealt to XCDs, images fastest within a tile
 };
 
 // Per-lane operands of one stage-1 K-step: the image and projection values of
@@ -124,8 +125,8 @@ __device__ __forceinline__ void split_item(const SplitArgs& sa, const uint4* __r
     const int tile = item / tile_items, rr = item - tile * tile_items;
     const int ti = tile / sa.n_ts, ts = tile - ti * sa.n_ts;
     const int cg = rr % ncg, pr = rr / ncg;
-    const int i = ti * sa.ti + pr / sa.ts;
-    const int slot = ts * sa.ts + pr % sa.ts;
+    const int i = ti * sa.ti + (sa.xcd ? pr % sa.ti : pr / sa.ts);
+    const int slot = ts * sa.ts + (sa.xcd ? pr / sa.ti : pr % sa.ts);
     if (i >= a.ni || slot >= nslots) return;   // uniform across the wave
     const int q = a.cand ? a.cand[(size_t)i * a.k + slot] : slot;
     const float2* O = a.ispec + (size_t)i * len;
@@ -406,10 +407,24 @@ __global__ __launch_bounds__(64 * WAVES, 1) void k_logpost_split(SplitArgs sa) {
   const int nF = sa.KS * NT * 2 * 64, nG = sa.MT * NT * 2 * 64;
   for (int e = threadIdx.x; e < nF + nG; e += 64 * WAVES) lds[e] = e < nF ? sa.F[e] : sa.G[e - nF];
   __syncthreads();
-  const int wave = blockIdx.x * WAVES + (threadIdx.x >> 6);
-  const int nwaves = gridDim.x * WAVES;
   const int n_items = sa.n_ti * sa.n_ts * sa.ti * sa.ts * sa.ncg;
-  for (int item = wave; item < n_items; item += nwaves) split_item<BF, NT, EW, LM>(sa, lds, lds + nF, item);
+  if (sa.xcd) {
+    // Workgroups are dealt to the 8 XCDs round-robin (each with its own L2):
+    // XCD x takes tiles x, x + 8, ... and its waves sweep one tile together,
+    // images fastest, so the tile's images stay in that L2 while its
+    // orientations stream through.
+    const int kx = min(8, (int)gridDim.x);   // groups present (every one has a workgroup)
+    const int x = blockIdx.x % kx;
+    const int nwg = (gridDim.x - x + kx - 1) / kx;
+    const int lw = (blockIdx.x / kx) * WAVES + (threadIdx.x >> 6), nw = nwg * WAVES;
+    const int tile_items = sa.ti * sa.ts * sa.ncg, n_tiles = sa.n_ti * sa.n_ts;
+    for (int t = x; t < n_tiles; t += kx)
+      for (int r = lw; r < tile_items; r += nw) split_item<BF, NT, EW, LM>(sa, lds, lds + nF, t * tile_items + r);
+  } else {
+    const int wave = blockIdx.x * WAVES + (threadIdx.x >> 6);
+    const int nwaves = gridDim.x * WAVES;
+    for (int item = wave; item < n_items; item += nwaves) split_item<BF, NT, EW, LM>(sa, lds, lds + nF, item);
+  }
 }
 
 // Persistent form over several jobs (boxes, shift windows, grids) in one
@@ -523,10 +538,11 @@ size_t split_smem(int nx, int ny, int S) {
 // workgroup (4 = one wave per SIMD with up to 512 registers, 8 = two per SIMD
 // with up to 256) and the load schedule of the K loop.
 struct Shape {
-  int ew, waves, lm;
+  int ew, waves, lm, xcd;
 };
-constexpr Shape kShapes[] = {{2, 4, kLoadPing}, {2, 8, kLoadNone}, {1, 8, kLoadNext}, {4, 4, kLoadNext},
-                             {2, 4, kLoadNext}, {4, 4, kLoadNone}, {2, 4, kLoadNone}};
+constexpr Shape kShapes[] = {{2, 4, kLoadPing, 0}, {2, 8, kLoadNone, 0}, {1, 8, kLoadNext, 0},
+                             {4, 4, kLoadNext, 0}, {2, 4, kLoadNext, 0}, {4, 4, kLoadNone, 0},
+                             {2, 4, kLoadNone, 0}, {4, 4, kLoadNext, 1}, {2, 4, kLoadNext, 1}};
 constexpr int kNumShapes = sizeof(kShapes) / sizeof(kShapes[0]);
 
 template <bool BF, int NT, int EW, int WAVES, int LM>
@@ -551,7 +567,9 @@ hipError_t launch_nt(hipStream_t s, const SplitArgs& sa, size_t smem, int ncu, i
     case 3: return launch_shape<BF, NT, 4, 4, kLoadNext>(s, sa, smem, ncu);
     case 4: return launch_shape<BF, NT, 2, 4, kLoadNext>(s, sa, smem, ncu);
     case 5: return launch_shape<BF, NT, 4, 4, kLoadNone>(s, sa, smem, ncu);
-    default: return launch_shape<BF, NT, 2, 4, kLoadNone>(s, sa, smem, ncu);
+    case 6: return launch_shape<BF, NT, 2, 4, kLoadNone>(s, sa, smem, ncu);
+    case 7: return launch_shape<BF, NT, 4, 4, kLoadNext>(s, sa, smem, ncu);
+    default: return launch_shape<BF, NT, 2, 4, kLoadNext>(s, sa, smem, ncu);
   }
 }
 
@@ -612,6 +630,7 @@ hipError_t launch_logpost_split(hipStream_t s, const LogpostArgs& a, bool bf16, 
   SplitArgs sa;
   uint4* tabs = nullptr;
   hipError_t e = make_split_args(s, a, bf16, kShapes[shape].ew, ti, ts, sa, tabs);
+  sa.xcd = kShapes[shape].xcd;
   if (e == hipSuccess) {
     const int NT = nt_for(a.S), ncu = device_cus();
     const size_t smem = split_smem(a.nx, a.ny, a.S);

@@ -12,8 +12,9 @@ namespace {
 
 constexpr int kProjWaves = 4;      // waves per projection workgroup (one per SIMD)
 constexpr int kProjTiles = 25;     // 16x16 output tiles per wave
-constexpr int kProjChunk = 4;      // spheres per LDS stage (one MFMA K-step)
+constexpr int kProjChunk = 8;      // spheres per LDS stage (two MFMA K-steps)
 constexpr int kProjSeg = 63;       // pixels per wave segment (64 boundaries)
+constexpr int kProjSuper = 2048;   // spheres whose rotated parameters sit in LDS at once
 
 typedef double d4 __attribute__((ext_vector_type(4)));
 
@@ -35,6 +36,8 @@ __global__ __launch_bounds__(64 * kProjWaves, 1) void k_project(const double* __
   __shared__ double ex[kProjChunk][kMaxBox];
   __shared__ double ey[kProjChunk][kMaxBox];
   __shared__ double rot[6];
+  __shared__ int ext[kProjChunk][4];   // pixel ranges (x lo, x hi, y lo, y hi) of each sphere
+  extern __shared__ double4 prm[];     // [kProjSuper]: rotated x, y, 1/(sqrt(2) sigma), weight
   const int q = blockIdx.y;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   if (tid == 0) {
@@ -57,7 +60,32 @@ __global__ __launch_bounds__(64 * kProjWaves, 1) void k_project(const double* __
 #pragma unroll
   for (int t = 0; t < kProjTiles; ++t) acc[t] = d4{0.0, 0.0, 0.0, 0.0};
   __syncthreads();
-  for (int a0 = 0; a0 < ns; a0 += kProjChunk) {
+  for (int s0 = 0; s0 < ns; s0 += kProjSuper) {
+   const int sn = min(kProjSuper, ns - s0);
+   // rotated centres and widths of this run of spheres, once per workgroup
+   __syncthreads();
+   for (int t = tid; t < sn; t += 64 * kProjWaves) {
+     const double* sp = spheres + 5 * (size_t)(s0 + t);
+     prm[t] = make_double4(rot[0] * sp[0] + rot[1] * sp[1] + rot[2] * sp[2],
+                           rot[3] * sp[0] + rot[4] * sp[1] + rot[5] * sp[2], 1.0 / (sqrt(2.0) * sp[3]), sp[4]);
+   }
+   __syncthreads();
+   for (int a0 = s0; a0 < s0 + sn; a0 += kProjChunk) {
+    // Beyond 12 sigma plus a pixel from its centre a sphere's pixel integrals
+    // are below erfc(8) ~ 1e-29 of its peak: segments and output tiles
+    // outside every sphere's range take no factors and no products.
+    if (tid < kProjChunk) {
+      int r4[4] = {1, 0, 1, 0};   // empty
+      if (a0 + tid < s0 + sn) {
+        const double4 pa = prm[a0 - s0 + tid];
+        const double R = (12.0 / (sqrt(2.0) * pa.z) + pixel) / pixel;   // 12 sigma + a pixel
+        const double cx = pa.x / pixel + nx / 2, cy = pa.y / pixel + ny / 2;
+        r4[0] = (int)fmax(floor(cx - R), -1.0); r4[1] = (int)fmin(ceil(cx + R), (double)nx);
+        r4[2] = (int)fmax(floor(cy - R), -1.0); r4[3] = (int)fmin(ceil(cy + R), (double)ny);
+      }
+      for (int k = 0; k < 4; ++k) ext[tid][k] = r4[k];
+    }
+    __syncthreads();
     // factors of this chunk: one (sphere, axis, 63-pixel segment) per wave pass
     for (int task = wave; task < tasks; task += kProjWaves) {
       const int a = task / (segx + segy), r = task - a * (segx + segy);
@@ -67,24 +95,25 @@ __global__ __launch_bounds__(64 * kProjWaves, 1) void k_project(const double* __
       const int p0 = lo + kProjSeg * (yaxis ? r - segx : r);
       const int n = yaxis ? ny : nx;
       double c = 0.0, inv = 0.0, wgt = 0.0;
-      const bool real = a0 + a < ns;
+      const bool real = a0 + a < s0 + sn;
       if (real) {
-        const double* sp = spheres + 5 * (a0 + a);
-        c = yaxis ? rot[3] * sp[0] + rot[4] * sp[1] + rot[5] * sp[2]
-                  : rot[0] * sp[0] + rot[1] * sp[1] + rot[2] * sp[2];
-        inv = 1.0 / (sqrt(2.0) * sp[3]);
-        wgt = yaxis ? sp[4] : 1.0;
+        const double4 pa = prm[a0 - s0 + a];
+        c = yaxis ? pa.y : pa.x;
+        inv = pa.z;
+        wgt = yaxis ? pa.w : 1.0;
       }
       // boundary p0 + lane lies at the lower edge of pixel p0 + lane
+      const int elo = ext[a][yaxis ? 2 : 0], ehi = ext[a][yaxis ? 3 : 1];
+      const bool far = p0 + kProjSeg - 1 < elo || p0 > ehi;   // uniform across the wave
       const double zb = (((p0 + lane) - n / 2) * pixel - h - c) * inv;
       const double az = fabs(zb);
-      const double eb = az < 27.3 ? erfc(az) : 0.0;   // erfc(27.3) < 2^-1074
+      const double eb = (!far && az < 27.3) ? erfc(az) : 0.0;   // erfc(27.3) < 2^-1074
       const double zn = __shfl_down(zb, 1, 64);
       const double en = __shfl_down(eb, 1, 64);
       const int p = p0 + lane;
       if (lane < kProjSeg && p < hi) {
         double v = 0.0;
-        if (real && p < n) {
+        if (real && !far && p < n) {
           if (zb > 0.0) v = 0.5 * (eb - en);           // both boundaries above the centre
           else if (zn < 0.0) v = 0.5 * (en - eb);      // both below
           else v = 0.5 * ((1.0 - eb) + (1.0 - en));    // straddles the centre
@@ -97,10 +126,23 @@ __global__ __launch_bounds__(64 * kProjWaves, 1) void k_project(const double* __
 #pragma unroll
     for (int ks = 0; ks < kProjChunk / 4; ++ks) {
       const int kk = 4 * ks + (lane >> 4), li = lane & 15;
+      // lane t decides whether some sphere of this K-step reaches the wave's
+      // tile t; one ballot gives the wave a uniform mask
+      bool reach = false;
+      if (lane < kProjTiles) {
+        const int tile = band0 + wave + kProjWaves * lane;
+        if (tile < band1) {
+          const int tr = tile / tcols, tc = tile - tr * tcols;
+          for (int a = 4 * ks; a < 4 * ks + 4; ++a)
+            reach = reach || (ext[a][0] <= 16 * tc + 15 && ext[a][1] >= 16 * tc && ext[a][2] <= 16 * tr + 15 &&
+                              ext[a][3] >= 16 * tr);
+        }
+      }
+      const uint64_t hit = __ballot(reach);
 #pragma unroll
       for (int t = 0; t < kProjTiles; ++t) {
         const int tile = band0 + wave + kProjWaves * t;
-        if (tile < band1) {   // uniform across the wave
+        if (tile < band1 && ((hit >> t) & 1)) {   // uniform across the wave
           const int tr = tile / tcols, tc = tile - tr * tcols;
           const double av = ey[kk][16 * (tr - tr0) + li];
           const double bv = ex[kk][16 * tc + li];
@@ -109,6 +151,7 @@ __global__ __launch_bounds__(64 * kProjWaves, 1) void k_project(const double* __
       }
     }
     __syncthreads();
+   }
   }
   // The FP64 16x16 result interleaves rows: D[i][j] sits in lane
   // j + 16 (i % 4), element i / 4 (unlike the FP32-output forms, where lane
@@ -435,7 +478,11 @@ hipError_t launch_project_images(hipStream_t s, const double* spheres, int ns, c
                                  int nq, int nx, int ny, double pixel, double* out_i0) {
   const int rb = (kProjWaves * kProjTiles) / ((nx + 15) / 16);
   dim3 grid(((ny + 15) / 16 + rb - 1) / rb, nq);
-  hipLaunchKernelGGL(k_project, grid, dim3(64 * kProjWaves), 0, s, spheres, ns, quats, nx, ny, pixel, out_i0);
+  const size_t smem = sizeof(double4) * kProjSuper;
+  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_project),
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_project, grid, dim3(64 * kProjWaves), smem, s, spheres, ns, quats, nx, ny, pixel, out_i0);
   return last();
 }
 
