@@ -401,14 +401,14 @@ __device__ __forceinline__ void split_item(const SplitArgs& sa, const uint4* __r
   }
 }
 
-template <bool BF, int NT, int EW, int WAVES, int LM>
+template <bool BF, int NT, int EW, int WAVES, int LM, bool XCD>
 __global__ __launch_bounds__(64 * WAVES, 1) void k_logpost_split(SplitArgs sa) {
   extern __shared__ uint4 lds[];
   const int nF = sa.KS * NT * 2 * 64, nG = sa.MT * NT * 2 * 64;
   for (int e = threadIdx.x; e < nF + nG; e += 64 * WAVES) lds[e] = e < nF ? sa.F[e] : sa.G[e - nF];
   __syncthreads();
   const int n_items = sa.n_ti * sa.n_ts * sa.ti * sa.ts * sa.ncg;
-  if (sa.xcd) {
+  if constexpr (XCD) {
     // Workgroups are dealt to the 8 XCDs round-robin (each with its own L2):
     // XCD x takes tiles x, x + 8, ... and its waves sweep one tile together,
     // images fastest, so the tile's images stay in that L2 while its
@@ -545,9 +545,9 @@ constexpr Shape kShapes[] = {{2, 4, kLoadPing, 0}, {2, 8, kLoadNone, 0}, {1, 8, 
                              {2, 4, kLoadNone, 0}, {4, 4, kLoadNext, 1}, {2, 4, kLoadNext, 1}};
 constexpr int kNumShapes = sizeof(kShapes) / sizeof(kShapes[0]);
 
-template <bool BF, int NT, int EW, int WAVES, int LM>
+template <bool BF, int NT, int EW, int WAVES, int LM, bool XCD = false>
 hipError_t launch_shape(hipStream_t s, const SplitArgs& sa, size_t smem, int ncu) {
-  auto kern = k_logpost_split<BF, NT, EW, WAVES, LM>;
+  auto kern = k_logpost_split<BF, NT, EW, WAVES, LM, XCD>;
   hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
   if (e != hipSuccess) return e;
@@ -568,8 +568,8 @@ hipError_t launch_nt(hipStream_t s, const SplitArgs& sa, size_t smem, int ncu, i
     case 4: return launch_shape<BF, NT, 2, 4, kLoadNext>(s, sa, smem, ncu);
     case 5: return launch_shape<BF, NT, 4, 4, kLoadNone>(s, sa, smem, ncu);
     case 6: return launch_shape<BF, NT, 2, 4, kLoadNone>(s, sa, smem, ncu);
-    case 7: return launch_shape<BF, NT, 4, 4, kLoadNext>(s, sa, smem, ncu);
-    default: return launch_shape<BF, NT, 2, 4, kLoadNext>(s, sa, smem, ncu);
+    case 7: return launch_shape<BF, NT, 4, 4, kLoadNext, true>(s, sa, smem, ncu);
+    default: return launch_shape<BF, NT, 2, 4, kLoadNext, true>(s, sa, smem, ncu);
   }
 }
 
