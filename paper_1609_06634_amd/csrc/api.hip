@@ -24,14 +24,13 @@ bool valid_box(int nx, int ny) {
 }
 
 // Launch shape of the split kernel: BIOEM_SPLIT_SHAPE overrides the default.
-int split_shape_for(bioem_ctx* ctx, int nx, int ny, int S, int nc) {
-  (void)ctx; (void)nx; (void)ny; (void)S; (void)nc;
+int split_shape_for(bool bf16) {
   const char* env = std::getenv("BIOEM_SPLIT_SHAPE");
   if (env) {
     const int v = std::atoi(env);
     if (v >= 0 && v < split_num_shapes()) return v;
   }
-  return 3;
+  return split_shape_for_ew(2, bf16);
 }
 
 // Items per transform chunk so that the FP64 scratch stays within budget.
@@ -59,7 +58,7 @@ struct Job {
   double log_prior = 0.0;
   bool has_cand = false;
   DevIn dctf, dcand;
-  DevMem table, B;
+  DevMem table, ttable, B;
   DevMem dlogp, dbest, dorient;
   double* d_logp = nullptr;
   bioem_best* d_best = nullptr;
@@ -125,6 +124,10 @@ bioem_status plan_job(bioem_ctx* ctx, const bioem_job& jb, int prec, int out_mem
   HIP_OR_FAIL(ctx, J.table.alloc(sizeof(float) * J.len * nc));
   HIP_OR_FAIL(ctx, J.B.alloc(sizeof(double) * (size_t)nq * nc));
   HIP_OR_FAIL(ctx, launch_ctf_table(s, J.dctf.as<double>(), nc, nx, ny, proj->pixel, J.table.as<float>()));
+  if (split) {
+    HIP_OR_FAIL(ctx, J.ttable.alloc(sizeof(float4) * tile_table_len(nx, ny) * nc));
+    HIP_OR_FAIL(ctx, launch_tile_table(s, J.table.as<float>(), nc, nx, ny, J.ttable.as<float4>()));
+  }
   HIP_OR_FAIL(ctx, launch_proj_norms(s, proj->spec, proj->expo, nq, J.table.as<float>(), nc, nx, ny,
                                      J.B.as<double>()));
   J.logp = jb.logp; J.best = jb.best; J.orient = jb.logp_orient;
@@ -144,6 +147,8 @@ LogpostArgs job_args(const Job& J, int i0, int cn, bioem_erec* rec) {
   a.ni = cn;
   a.pspec = J.proj->spec; a.pexpo = J.proj->expo; a.nq = J.nq;
   a.table = J.table.as<float>(); a.B = J.B.as<double>(); a.nc = J.nc;
+  a.itile = J.imgs->tile + tile_spec_len(J.nx, J.ny) * i0; a.ptile = J.proj->tile;
+  a.ttile = J.ttable.p ? J.ttable.as<float4>() : nullptr;
   a.nx = J.nx; a.ny = J.ny; a.S = J.S; a.ldy = spec_ld(J.ny);
   a.cand = J.has_cand ? J.dcand.as<int32_t>() + (size_t)i0 * J.k : nullptr; a.k = J.k;
   a.rec = rec;
@@ -182,7 +187,7 @@ struct SplitCfg {
   int shape, ew, ti, ts;
 };
 
-constexpr int kTuneEW[] = {4, 2};
+constexpr int kTuneEW[] = {2, 4};   // the first is the default
 constexpr int kTuneTiles[][2] = {{16, 128}, {8, 256}, {32, 64}, {4, 512}};
 
 int ilog2(int v) {
@@ -205,11 +210,11 @@ bioem_status tune_job(bioem_ctx* ctx, const Job& J, int prec, bioem_tuning& out)
   HIP_OR_FAIL(ctx, hipEventCreate(&e1));
   const double evals = (double)ni_s * nslots_s * J.nc;
   double best = 1e300, def = 1e300;
-  int bew = 4, bti = kTuneTiles[0][0], bts = kTuneTiles[0][1];
+  int bew = kTuneEW[0], bti = kTuneTiles[0][0], bts = kTuneTiles[0][1];
   hipError_t err = hipSuccess;
   for (int ew : kTuneEW)
     for (const auto& t : kTuneTiles) {
-      const int shape = split_shape_for_ew(ew);
+      const int shape = split_shape_for_ew(ew, bf16);
       float ms = 0.0f;
       for (int rep = 0; rep < 2 && err == hipSuccess; ++rep) {   // first run warms the caches
         err = hipEventRecord(e0, s);
@@ -220,7 +225,7 @@ bioem_status tune_job(bioem_ctx* ctx, const Job& J, int prec, bioem_tuning& out)
       }
       if (err != hipSuccess) break;
       const double ns = ms * 1e6 / evals;
-      if (ew == 4 && t[0] == kTuneTiles[0][0] && t[1] == kTuneTiles[0][1]) def = ns;
+      if (ew == kTuneEW[0] && t[0] == kTuneTiles[0][0] && t[1] == kTuneTiles[0][1]) def = ns;
       if (ns < best) { best = ns; bew = ew; bti = t[0]; bts = t[1]; }
     }
   (void)hipEventDestroy(e0);
@@ -234,22 +239,23 @@ bioem_status tune_job(bioem_ctx* ctx, const Job& J, int prec, bioem_tuning& out)
 }
 
 bioem_status split_cfg(bioem_ctx* ctx, const Job& J, int prec, SplitCfg& cfg) {
-  cfg = SplitCfg{split_shape_for(ctx, J.nx, J.ny, J.S, J.nc), 4, 0, 0};
+  const bool bf16 = prec == BIOEM_PREC_SPLIT_BF16;
+  cfg = SplitCfg{split_shape_for(bf16), 2, 0, 0};
   if (std::getenv("BIOEM_SPLIT_SHAPE") || !ctx->autotune) {
-    cfg.ew = cfg.shape == split_shape_for_ew(2) ? 2 : 4;
+    cfg.ew = split_shape_ew(cfg.shape);
     return BIOEM_OK;
   }
   const int lq = ilog2(J.nq);
   for (const bioem_tuning& t : ctx->tuned)
     if (t.nx == J.nx && t.ny == J.ny && t.max_shift == J.S && t.nq_log2 == lq && t.prec == prec) {
-      cfg = SplitCfg{split_shape_for_ew(t.ew), t.ew, t.tile_images, t.tile_slots};
+      cfg = SplitCfg{split_shape_for_ew(t.ew, bf16), t.ew, t.tile_images, t.tile_slots};
       return BIOEM_OK;
     }
   bioem_tuning t;
   const bioem_status st = tune_job(ctx, J, prec, t);
   if (st != BIOEM_OK) return st;
   ctx->tuned.push_back(t);
-  cfg = SplitCfg{split_shape_for_ew(t.ew), t.ew, t.tile_images, t.tile_slots};
+  cfg = SplitCfg{split_shape_for_ew(t.ew, bf16), t.ew, t.tile_images, t.tile_slots};
   return BIOEM_OK;
 }
 
@@ -420,6 +426,7 @@ void bioem_free_proj(bioem_proj* p) {
   if (!p) return;
   (void)hipSetDevice(p->device);
   if (p->spec) (void)hipFree(p->spec);
+  if (p->tile) (void)hipFree(p->tile);
   if (p->expo) (void)hipFree(p->expo);
   delete p;
 }
@@ -428,6 +435,7 @@ void bioem_free_imgs(bioem_imgs* p) {
   if (!p) return;
   (void)hipSetDevice(p->device);
   if (p->spec) (void)hipFree(p->spec);
+  if (p->tile) (void)hipFree(p->tile);
   if (p->expo) (void)hipFree(p->expo);
   if (p->stats) (void)hipFree(p->stats);
   delete p;
@@ -500,12 +508,14 @@ bioem_status bioem_project(bioem_ctx* ctx, const double* spheres, int32_t ns, co
   bioem_proj* p = new (std::nothrow) bioem_proj;
   if (!p) return fail(ctx, BIOEM_ENOMEM, "bioem_project: host allocation");
   p->n = nq; p->nx = nx; p->ny = ny; p->pixel = pixel_A; p->device = ctx->device;
+  const size_t tlen = tile_spec_len(nx, ny);
   hipError_t e = hipMalloc(reinterpret_cast<void**>(&p->spec), sizeof(float2) * slen * nq);
+  if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&p->tile), sizeof(float4) * tlen * nq);
   if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&p->expo), sizeof(int32_t) * nq);
   if (e != hipSuccess) {
     bioem_free_proj(p);
     return fail(ctx, BIOEM_ENOMEM, "bioem_project: device allocation of %zu MB failed",
-                (sizeof(float2) * slen * nq) >> 20);
+                ((sizeof(float2) * slen + sizeof(float4) * tlen) * nq) >> 20);
   }
   const size_t per = (size_t)nx * ny * 8 + (size_t)ny * mh * 16 + len * 16;
   const int chunk = chunk_items(nq, per);
@@ -519,6 +529,7 @@ bioem_status bioem_project(bioem_ctx* ctx, const double* spheres, int32_t ns, co
                               pixel_A, i0.as<double>());
     if (e == hipSuccess) e = launch_rdft2(s, i0.as<double>(), nullptr, cn, nx, ny, rows.as<double2>(), s64.as<double2>());
     if (e == hipSuccess) e = launch_spec_store(s, s64.as<double2>(), cn, nx, ny, p->spec + slen * q0, p->expo + q0);
+    if (e == hipSuccess) e = launch_tile_spec(s, p->spec + slen * q0, cn, nx, ny, p->tile + tlen * q0);
   }
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   if (e != hipSuccess) {
@@ -546,7 +557,9 @@ bioem_status bioem_prepare_images(bioem_ctx* ctx, const float* imgs, int32_t ni,
   bioem_imgs* p = new (std::nothrow) bioem_imgs;
   if (!p) return fail(ctx, BIOEM_ENOMEM, "bioem_prepare_images: host allocation");
   p->n = ni; p->nx = nx; p->ny = ny; p->device = ctx->device;
+  const size_t tlen = tile_spec_len(nx, ny);
   hipError_t e = hipMalloc(reinterpret_cast<void**>(&p->spec), sizeof(float2) * slen * ni);
+  if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&p->tile), sizeof(float4) * tlen * ni);
   if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&p->expo), sizeof(int32_t) * ni);
   if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&p->stats), sizeof(double) * 3 * ni);
   if (e != hipSuccess) {
@@ -569,6 +582,7 @@ bioem_status bioem_prepare_images(bioem_ctx* ctx, const float* imgs, int32_t ni,
     if (e == hipSuccess) e = launch_image_stats(s, src, cn, (int)npix, p->stats + 3 * (size_t)i0);
     if (e == hipSuccess) e = launch_rdft2(s, nullptr, src, cn, nx, ny, rows.as<double2>(), s64.as<double2>());
     if (e == hipSuccess) e = launch_spec_store(s, s64.as<double2>(), cn, nx, ny, p->spec + slen * i0, p->expo + i0);
+    if (e == hipSuccess) e = launch_tile_spec(s, p->spec + slen * i0, cn, nx, ny, p->tile + tlen * i0);
     if (e == hipSuccess && in_mem == BIOEM_MEM_HOST) e = hipStreamSynchronize(s);  // stage reuse
   }
   if (e == hipSuccess) e = hipStreamSynchronize(s);

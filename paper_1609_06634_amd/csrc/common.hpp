@@ -29,10 +29,20 @@ struct bioem_ctx {
 // zero-padded to spec_ld(ny) rows, scaled by
 // 2^-expo[item] so that every |value| <= 1 (the split-precision kernels need
 // a bounded range; the scale is undone in FP64 in the likelihood epilogue).
+//
+// The split-precision kernel reads a second copy in its matrix-fragment
+// order (tile_spec_len(nx, ny) float4 per item): for column tile mt (16
+// columns m = 16 mt + j, m < nx/2), row step ks (32 rows l) and part r, the
+// 64 lanes' values are contiguous, so every load instruction of a wave reads
+// 1 KB in one piece:
+//   tile[item][(mt*KS + ks)*4 + r][lane] = (Z(l), Z(l+1)) as (re, im, re, im),
+//   lane = j + 16 g, l = 32 ks + 8 g + 2 r; zero for m >= nx/2 or l >= ny.
+// Column nx/2 is read from the column-major copy.
 struct bioem_proj {
   int32_t n = 0, nx = 0, ny = 0;
   double pixel = 0.0;         // A per pixel (sets the CTF frequency scale)
   float2* spec = nullptr;     // [n][nx/2+1][spec_ld(ny)]
+  float4* tile = nullptr;     // [n][tile_spec_len(nx, ny)]
   int32_t* expo = nullptr;    // [n]
   int device = 0;
 };
@@ -40,6 +50,7 @@ struct bioem_proj {
 struct bioem_imgs {
   int32_t n = 0, nx = 0, ny = 0;
   float2* spec = nullptr;     // [n][nx/2+1][spec_ld(ny)]
+  float4* tile = nullptr;     // [n][tile_spec_len(nx, ny)]
   int32_t* expo = nullptr;    // [n]
   double* stats = nullptr;    // [n][3]: C_o, C_oo, A
   int device = 0;
@@ -71,6 +82,10 @@ hipError_t launch_rdft2(hipStream_t s, const double* real_in, const float* real_
 hipError_t launch_spec_store(hipStream_t s, const double2* spec64, int n, int nx, int ny,
                              float2* spec, int32_t* expo);
 hipError_t launch_image_stats(hipStream_t s, const float* imgs, int n, int npix, double* stats);
+// Fragment-order copies: complex spectra [n][nx/2+1][spec_ld(ny)] -> [n][tile_spec_len],
+// real tables [n][nx/2+1][spec_ld(ny)] -> [n][tile_table_len] (rows l = 32 ks + 8 g + 4 r .. +3, r < 2).
+hipError_t launch_tile_spec(hipStream_t s, const float2* spec, int n, int nx, int ny, float4* tile);
+hipError_t launch_tile_table(hipStream_t s, const float* table, int n, int nx, int ny, float4* tile);
 hipError_t launch_render(hipStream_t s, const float2* spec, const int32_t* expo, int n, int nx,
                          int ny, double pixel, const double* ctf, const int32_t* shifts,
                          const double* norm_offset, const float* noise, double snr,
@@ -93,6 +108,7 @@ struct LogpostArgs {
   const float2* ispec; const int32_t* iexpo; const double* istats; int ni;   // image chunk
   const float2* pspec; const int32_t* pexpo; int nq;                        // all projections
   const float* table; const double* B; int nc;
+  const float4* itile; const float4* ptile; const float4* ttile;          // fragment-order copies
   int nx, ny, S, ldy;              // ldy = spec_ld(ny)
   const int32_t* cand; int k;     // [ni][k] chunk-relative rows, or null
   bioem_erec* rec;                // [ni][nq or k][nc]
@@ -107,7 +123,10 @@ constexpr size_t kMaxSmem = 160 * 1024;
 // item tile (images x orientation slots), 0 = default.
 hipError_t launch_logpost_split(hipStream_t s, const LogpostArgs& a, bool bf16, int shape, int ti, int ts);
 int split_num_shapes();
-int split_shape_for_ew(int ew);   // the one-wave-per-SIMD variant with ew CTF sets per item
+// The default one-wave-per-SIMD variant with ew CTF sets per item, and the
+// item width of a variant.
+int split_shape_for_ew(int ew, bool bf16);
+int split_shape_ew(int shape);
 // One persistent launch over several jobs; ew in {2, 4} CTF sets per item.
 struct BatchJob {
   LogpostArgs a;
@@ -135,6 +154,15 @@ hipError_t launch_finalize(hipStream_t s, const FinalizeArgs& f);
 // Stored spectrum columns (and CTF table columns) are padded with zeros to a
 // multiple of 32 rows, the K-step of the matrix-core transform.
 __host__ __device__ static inline int spec_ld(int ny) { return (ny + 31) & ~31; }
+// Column tiles (16 columns below nx/2) and row steps (32 rows) of the split kernel.
+__host__ __device__ static inline int split_mt(int nx) { return (nx / 2 + 15) / 16; }
+__host__ __device__ static inline int split_ks(int ny) { return (ny + 31) / 32; }
+__host__ __device__ static inline size_t tile_spec_len(int nx, int ny) {
+  return (size_t)split_mt(nx) * split_ks(ny) * 4 * 64;
+}
+__host__ __device__ static inline size_t tile_table_len(int nx, int ny) {
+  return (size_t)split_mt(nx) * split_ks(ny) * 2 * 64;
+}
 
 // exp(2 pi i t / n) in FP64 with the argument reduced exactly (t in [0, n)).
 BIOEM_DEV double2 twiddle64(long t, int n) {

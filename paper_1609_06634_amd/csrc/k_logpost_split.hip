@@ -78,13 +78,38 @@ struct Step {
   float t[EW][8];
 };
 
+// K-step `step` (= mt * KS + ks) of this lane from the fragment-order copies:
+// four contiguous 1 KB pieces per spectrum and two per CTF table.
 template <int EW>
-__device__ __forceinline__ void load_step(Step<EW>& st, const float2* Oc, const float2* Pc,
-                                          const float* const (&Tc)[EW], int l0) {
-  load8c(Oc, l0, st.o);
-  load8c(Pc, l0, st.p);
+__device__ __forceinline__ void load_spectra(Step<EW>& st, const float4* __restrict__ Ot,
+                                             const float4* __restrict__ Pt, int step, int lane) {
+  const size_t c = (size_t)step * 256 + lane;
 #pragma unroll
-  for (int e = 0; e < EW; ++e) load8r(Tc[e], l0, st.t[e]);
+  for (int r = 0; r < 4; ++r) {
+    const float4 v = Ot[c + 64 * r], w = Pt[c + 64 * r];
+    st.o[2 * r] = make_float2(v.x, v.y);
+    st.o[2 * r + 1] = make_float2(v.z, v.w);
+    st.p[2 * r] = make_float2(w.x, w.y);
+    st.p[2 * r + 1] = make_float2(w.z, w.w);
+  }
+}
+
+template <int EW>
+__device__ __forceinline__ void load_tables(Step<EW>& st, const float4* const (&Tt)[EW], int step, int lane) {
+  const size_t ct = (size_t)step * 128 + lane;
+#pragma unroll
+  for (int e = 0; e < EW; ++e) {
+    const float4 v = Tt[e][ct], w = Tt[e][ct + 64];
+    st.t[e][0] = v.x; st.t[e][1] = v.y; st.t[e][2] = v.z; st.t[e][3] = v.w;
+    st.t[e][4] = w.x; st.t[e][5] = w.y; st.t[e][6] = w.z; st.t[e][7] = w.w;
+  }
+}
+
+template <int EW>
+__device__ __forceinline__ void load_step(Step<EW>& st, const float4* __restrict__ Ot, const float4* __restrict__ Pt,
+                                          const float4* const (&Tt)[EW], int step, int lane) {
+  load_spectra<EW>(st, Ot, Pt, step, lane);
+  load_tables<EW>(st, Tt, step, lane);
 }
 
 // One work item: image i, orientation slot, CTF group cg (EW CTF sets).
@@ -131,6 +156,9 @@ __device__ __forceinline__ void split_item(const SplitArgs& sa, const uint4* __r
     const int q = a.cand ? a.cand[(size_t)i * a.k + slot] : slot;
     const float2* O = a.ispec + (size_t)i * len;
     const float2* Pq = a.pspec + (size_t)q * len;
+    const size_t tlen = tile_spec_len(nx, ny), ttlen = tile_table_len(nx, ny);
+    const float4* Ot = a.itile + (size_t)i * tlen;
+    const float4* Pt = a.ptile + (size_t)q * tlen;
     const double A = a.istats[3 * i + 2];
     const int esc = 2 * (a.iexpo[i] + a.pexpo[q]);
     const int c0 = cg * EW;
@@ -147,34 +175,22 @@ __device__ __forceinline__ void split_item(const SplitArgs& sa, const uint4* __r
 #pragma unroll
           for (int y = 0; y < NT; ++y) acc2[e][x][y] = f4{0.f, 0.f, 0.f, 0.f};
 
-      // this lane's spectrum column (stage-1 row) of m-tile mt
-      auto cols_of = [&](int mt, const float2*& Oc, const float2*& Pc, const float* (&Tc)[EW]) {
-        const int s = 16 * mt + li;
-        const int col = s < half ? s : 0;
-        Oc = O + (size_t)col * ldy;
-        Pc = Pq + (size_t)col * ldy;
+      // CTF tables of the group in fragment order (slots past nx/2 hold
+      // zeros in every copy, so their products vanish)
+      const float4* Tt[EW];
 #pragma unroll
-        for (int e = 0; e < EW; ++e) Tc[e] = a.table + (size_t)min(c0 + e, a.nc - 1) * len + (size_t)col * ldy;
-      };
+      for (int e = 0; e < EW; ++e) Tt[e] = a.ttile + (size_t)min(c0 + e, a.nc - 1) * ttlen;
       // with the in-place schedule the loaded step carries across m-tiles:
       // the first step of the next tile is in flight during stage 2
       Step<EW> st;
-      if constexpr (LM == kLoadNext) {
-        const float2 *Oc, *Pc;
-        const float* Tc[EW];
-        cols_of(0, Oc, Pc, Tc);
-        load_step<EW>(st, Oc, Pc, Tc, 8 * lg);
-      }
+      if constexpr (LM == kLoadNext) load_step<EW>(st, Ot, Pt, Tt, 0, lane);
       for (int mt = 0; mt < MT; ++mt) {
         f4 acc1[EW][NT][2];
 #pragma unroll
         for (int e = 0; e < EW; ++e)
 #pragma unroll
           for (int x = 0; x < NT; ++x) acc1[e][x][0] = acc1[e][x][1] = f4{0.f, 0.f, 0.f, 0.f};
-        const bool live = 16 * mt + li < half;
-        const float2 *Oc, *Pc;
-        const float* Tc[EW];
-        cols_of(mt, Oc, Pc, Tc);
+        const int st0 = mt * KS;             // flat index of the tile's first K-step
         const bool pk = mt == 0;             // slot 0 of this tile carries columns 0 and nx/2
         // prep: the K-step's conjugate products, CTF-weighted and split
         // into hi/lo operands (consumes the loaded step); mma: its products
@@ -184,7 +200,7 @@ __device__ __forceinline__ void split_item(const SplitArgs& sa, const uint4* __r
 #pragma unroll
           for (int r = 0; r < 8; ++r) {
             const float2 o = cur.o[r], p = cur.p[r];
-            w0[r] = live ? make_float2(o.x * p.x + o.y * p.y, o.x * p.y - o.y * p.x) : make_float2(0.f, 0.f);
+            w0[r] = make_float2(o.x * p.x + o.y * p.y, o.x * p.y - o.y * p.x);
           }
           float zr[EW][8], zi[EW][8];
 #pragma unroll
@@ -264,19 +280,19 @@ __device__ __forceinline__ void split_item(const SplitArgs& sa, const uint4* __r
           // two register sets in ping-pong: the loads of the next K-step are
           // in flight while this one computes, with no copies between sets
           Step<EW> sa0, sa1;
-          load_step<EW>(sa0, Oc, Pc, Tc, 8 * lg);
+          load_step<EW>(sa0, Ot, Pt, Tt, st0, lane);
           for (int ks = 0; ks < KS; ks += 2) {
-            if (ks + 1 < KS) load_step<EW>(sa1, Oc, Pc, Tc, 32 * (ks + 1) + 8 * lg);
+            if (ks + 1 < KS) load_step<EW>(sa1, Ot, Pt, Tt, st0 + ks + 1, lane);
             body(sa0, ks);
             if (ks + 1 < KS) {
-              if (ks + 2 < KS) load_step<EW>(sa0, Oc, Pc, Tc, 32 * (ks + 2) + 8 * lg);
+              if (ks + 2 < KS) load_step<EW>(sa0, Ot, Pt, Tt, st0 + ks + 2, lane);
               body(sa1, ks + 1);
             }
           }
         } else if constexpr (LM == kLoadNone) {
           for (int ks = 0; ks < KS; ++ks) {
             Step<EW> st;
-            load_step<EW>(st, Oc, Pc, Tc, 32 * ks + 8 * lg);
+            load_step<EW>(st, Ot, Pt, Tt, st0 + ks, lane);
             body(st, ks);
           }
         } else {
@@ -286,14 +302,8 @@ __device__ __forceinline__ void split_item(const SplitArgs& sa, const uint4* __r
           for (int ks = 0; ks < KS; ++ks) {
             V zrh[EW], zrl[EW], zih[EW], zil[EW];
             prep(st, ks, zrh, zrl, zih, zil);
-            if (ks + 1 < KS) {
-              load_step<EW>(st, Oc, Pc, Tc, 32 * (ks + 1) + 8 * lg);
-            } else if (mt + 1 < MT) {
-              const float2 *On, *Pn;
-              const float* Tn[EW];
-              cols_of(mt + 1, On, Pn, Tn);
-              load_step<EW>(st, On, Pn, Tn, 8 * lg);
-            }
+            // the next K-step in flat order (the next tile's first after the last)
+            if (st0 + ks + 1 < MT * KS) load_step<EW>(st, Ot, Pt, Tt, st0 + ks + 1, lane);
             mma(ks, zrh, zrl, zih, zil);
           }
         }
@@ -458,9 +468,8 @@ __global__ __launch_bounds__(64 * WAVES, 1) void k_logpost_batch(const JobDesc* 
       cur = j;
     }
     const int item = (blk - jd.block0) * WAVES + (threadIdx.x >> 6);
-    // the bf16 split needs more registers: its three variants fit only
-    // with the plain load schedule
-    constexpr int LM = BF ? kLoadNone : kLoadNext;
+    // two waves per SIMD: each K-step loaded just before use
+    constexpr int LM = kLoadNone;
     switch (jd.nt) {   // uniform across the workgroup
       case 1: split_item<BF, 1, EW, LM>(jd.sa, lds, lds + nF, item); break;
       case 2: split_item<BF, 2, EW, LM>(jd.sa, lds, lds + nF, item); break;
@@ -542,7 +551,8 @@ struct Shape {
 };
 constexpr Shape kShapes[] = {{2, 4, kLoadPing, 0}, {2, 8, kLoadNone, 0}, {1, 8, kLoadNext, 0},
                              {4, 4, kLoadNext, 0}, {2, 4, kLoadNext, 0}, {4, 4, kLoadNone, 0},
-                             {2, 4, kLoadNone, 0}, {4, 4, kLoadNext, 1}, {2, 4, kLoadNext, 1}};
+                             {2, 4, kLoadNone, 0}, {4, 4, kLoadNext, 1}, {2, 4, kLoadNext, 1},
+                             {2, 8, kLoadNext, 0}, {2, 8, kLoadNone, 1}};
 constexpr int kNumShapes = sizeof(kShapes) / sizeof(kShapes[0]);
 
 template <bool BF, int NT, int EW, int WAVES, int LM, bool XCD = false>
@@ -569,7 +579,9 @@ hipError_t launch_nt(hipStream_t s, const SplitArgs& sa, size_t smem, int ncu, i
     case 5: return launch_shape<BF, NT, 4, 4, kLoadNone>(s, sa, smem, ncu);
     case 6: return launch_shape<BF, NT, 2, 4, kLoadNone>(s, sa, smem, ncu);
     case 7: return launch_shape<BF, NT, 4, 4, kLoadNext, true>(s, sa, smem, ncu);
-    default: return launch_shape<BF, NT, 2, 4, kLoadNext, true>(s, sa, smem, ncu);
+    case 8: return launch_shape<BF, NT, 2, 4, kLoadNext, true>(s, sa, smem, ncu);
+    case 9: return launch_shape<BF, NT, 2, 8, kLoadNext>(s, sa, smem, ncu);
+    default: return launch_shape<BF, NT, 2, 8, kLoadNone, true>(s, sa, smem, ncu);
   }
 }
 
@@ -642,15 +654,19 @@ hipError_t launch_logpost_split(hipStream_t s, const LogpostArgs& a, bool bf16, 
   return e != hipSuccess ? e : f;
 }
 
-int split_shape_for_ew(int ew) {
-  for (int k = 0; k < kNumShapes; ++k)
-    if (kShapes[k].ew == ew && kShapes[k].waves == 4 && kShapes[k].lm == kLoadNext) return k;
-  return 3;
+int split_shape_for_ew(int ew, bool bf16) {
+  // two CTF sets: two waves per SIMD (the other wave covers load latency);
+  // four: one wave per SIMD with every register, where the bf16 split
+  // spills under next-step loads
+  if (ew == 2) return 1;
+  return bf16 ? 5 : 3;
 }
 
+int split_shape_ew(int shape) { return shape >= 0 && shape < kNumShapes ? kShapes[shape].ew : 4; }
+
 hipError_t launch_logpost_batch(hipStream_t s, const BatchJob* jobs, int njobs, bool bf16) {
-  constexpr int kWaves = 4;
-  constexpr int kBatchEW = 4;
+  constexpr int kWaves = 8;     // two waves per SIMD, as the default single-job variant
+  constexpr int kBatchEW = 2;
   if (njobs < 1) return hipErrorInvalidValue;
   std::vector<JobDesc> desc(njobs);
   std::vector<uint4*> tabs(njobs, nullptr);

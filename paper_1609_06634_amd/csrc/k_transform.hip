@@ -535,6 +535,63 @@ hipError_t launch_autocorr(hipStream_t s, const float* imgs, int n, int nx, int 
   return last();
 }
 
+// Fragment-order copy of complex spectra: one float4 (two complex values) per
+// thread, written contiguously.
+__global__ __launch_bounds__(256) void k_tile_spec(const float2* __restrict__ spec, long total, int nx, int ny,
+                                                   float4* __restrict__ tile) {
+  const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= total) return;
+  const int KS = split_ks(ny), ldy = spec_ld(ny), half = nx / 2;
+  const long per = (long)tile_spec_len(nx, ny);
+  const long item = idx / per;
+  const int w = (int)(idx - item * per);
+  const int lane = w & 63, r = (w >> 6) & 3, step = w >> 8;
+  const int mt = step / KS, ks = step - mt * KS;
+  const int m = 16 * mt + (lane & 15), l = 32 * ks + 8 * (lane >> 4) + 2 * r;
+  float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+  if (m < half) {
+    const float2* c = spec + (size_t)item * (nx / 2 + 1) * ldy + (size_t)m * ldy;
+    const float2 a = c[l], b = c[l + 1];   // l + 1 < 32 KS = ldy; rows past ny are stored zeros
+    v = make_float4(a.x, a.y, b.x, b.y);
+  }
+  tile[idx] = v;
+}
+
+// Fragment-order copy of real tables: four consecutive rows per float4.
+__global__ __launch_bounds__(256) void k_tile_table(const float* __restrict__ table, long total, int nx, int ny,
+                                                    float4* __restrict__ tile) {
+  const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= total) return;
+  const int KS = split_ks(ny), ldy = spec_ld(ny), half = nx / 2;
+  const long per = (long)tile_table_len(nx, ny);
+  const long item = idx / per;
+  const int w = (int)(idx - item * per);
+  const int lane = w & 63, r = (w >> 6) & 1, step = w >> 7;
+  const int mt = step / KS, ks = step - mt * KS;
+  const int m = 16 * mt + (lane & 15), l = 32 * ks + 8 * (lane >> 4) + 4 * r;
+  float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+  if (m < half) {
+    const float* c = table + (size_t)item * (nx / 2 + 1) * ldy + (size_t)m * ldy + l;
+    v = make_float4(c[0], c[1], c[2], c[3]);
+  }
+  tile[idx] = v;
+}
+
+hipError_t launch_tile_spec(hipStream_t s, const float2* spec, int n, int nx, int ny, float4* tile) {
+  const long total = (long)n * (long)tile_spec_len(nx, ny);
+  if (total == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_tile_spec, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, spec, total, nx, ny, tile);
+  return last();
+}
+
+hipError_t launch_tile_table(hipStream_t s, const float* table, int n, int nx, int ny, float4* tile) {
+  const long total = (long)n * (long)tile_table_len(nx, ny);
+  if (total == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_tile_table, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, table, total, nx, ny,
+                     tile);
+  return last();
+}
+
 hipError_t launch_ctf_table(hipStream_t s, const double* ctf, int nc, int nx, int ny, double pixel,
                             float* table) {
   const int len = (nx / 2 + 1) * spec_ld(ny);
