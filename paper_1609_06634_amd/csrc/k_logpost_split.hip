@@ -467,13 +467,15 @@ __global__ __launch_bounds__(64 * WAVES, 1) void k_logpost_batch(const JobDesc* 
       __syncthreads();
       cur = j;
     }
-    const int item = (blk - jd.block0) * WAVES + (threadIdx.x >> 6);
+    const int item = (blk - jd.block0) * WAVES + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    // the job's arguments as a value (scalar registers), not re-read from the table
+    const SplitArgs sa = jd.sa;
     // two waves per SIMD: each K-step loaded just before use
     constexpr int LM = kLoadNone;
     switch (jd.nt) {   // uniform across the workgroup
-      case 1: split_item<BF, 1, EW, LM>(jd.sa, lds, lds + nF, item); break;
-      case 2: split_item<BF, 2, EW, LM>(jd.sa, lds, lds + nF, item); break;
-      default: split_item<BF, 3, EW, LM>(jd.sa, lds, lds + nF, item); break;
+      case 1: split_item<BF, 1, EW, LM>(sa, lds, lds + nF, item); break;
+      case 2: split_item<BF, 2, EW, LM>(sa, lds, lds + nF, item); break;
+      default: split_item<BF, 3, EW, LM>(sa, lds, lds + nF, item); break;
     }
   }
 }
