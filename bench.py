@@ -136,6 +136,8 @@ def main() -> int:
     ap.add_argument("--epochs", type=int, default=4)
     ap.add_argument("--topk", type=int, default=256)
     ap.add_argument("--tau", type=float, default=0.5)
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="mixed workload: default launch shape and item tiles for every job")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB three times (the reference "
                          "kernel for scaling HBM traffic counters) and exit")
@@ -301,7 +303,7 @@ def run_mixed(args, P, ctx, torch, dev) -> int:
             h.free()
         return outs
 
-    ctx.set_autotune(True)
+    ctx.set_autotune(not args.no_autotune)
     res = {}
     for mode in ("persistent", "per_job"):
         for w in range(args.warmup):
@@ -334,7 +336,7 @@ def run_mixed(args, P, ctx, torch, dev) -> int:
             "config": {"workload": f"mixed sizes: 96/128/180/224 px x {per} images each, two models "
                                    "(1000 and 2500 spheres), grids (1152,4) (2304,8) (3456,12) "
                                    "(4608,16), shifts 8/11/16/20, one persistent launch",
-                       "evals_per_step": evals, "prec": args.prec,
+                       "evals_per_step": evals, "prec": args.prec, "autotune": not args.no_autotune,
                        "step": "bioem_project + bioem_prepare_images + bioem_logpost_batch"},
             "roofline": {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP32_TFLOPS,
                          "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_TFLOPS, 4),

@@ -195,7 +195,7 @@ bioem_status bioem_logpost_batch(bioem_ctx* ctx, const bioem_job* jobs, int32_t 
  * item, item tile of images x orientations).  While enabled, the first
  * bioem_logpost / bioem_logpost_batch call that meets a new key
  * (nx, ny, S, orientation-count bucket floor(log2 nq), precision) times every
- * candidate shape on a sample of that call's own work (up to 32 images x 512
+ * candidate shape on a sample of that call's own work (up to 128 images x 2048
  * orientations) and keeps the fastest for the context's lifetime; later calls
  * with the key use it.  Disabled (the default): a fixed default shape.
  * Results do not depend on the shape beyond floating-point summation order. */

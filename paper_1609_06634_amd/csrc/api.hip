@@ -188,7 +188,7 @@ struct SplitCfg {
 };
 
 constexpr int kTuneEW[] = {2, 4};   // the first is the default
-constexpr int kTuneTiles[][2] = {{16, 128}, {8, 256}, {32, 64}, {4, 512}};
+constexpr int kTuneTiles[][2] = {{16, 128}, {8, 256}, {32, 64}, {4, 512}};   // the first is the default
 
 int ilog2(int v) {
   int r = 0;
@@ -199,8 +199,10 @@ int ilog2(int v) {
 bioem_status tune_job(bioem_ctx* ctx, const Job& J, int prec, bioem_tuning& out) {
   hipStream_t s = ctx->stream;
   const bool bf16 = prec == BIOEM_PREC_SPLIT_BF16;
-  const int ni_s = std::min(J.ni, 32);
-  const int nslots_s = J.has_cand ? J.k : std::min(J.nq, 512);
+  // a sample large enough that the item tiles meet the caches as in the
+  // full job (a few hundred thousand evaluations per candidate)
+  const int ni_s = std::min(J.ni, 128);
+  const int nslots_s = J.has_cand ? J.k : std::min(J.nq, 2048);
   DevMem rec;
   HIP_OR_FAIL(ctx, rec.alloc(sizeof(bioem_erec) * (size_t)ni_s * nslots_s * J.nc));
   LogpostArgs a = job_args(J, 0, ni_s, rec.as<bioem_erec>());
