@@ -332,6 +332,7 @@ __device__ __forceinline__ void split_item(const SplitArgs& sa, const uint4* __r
             }
             split8<BF>(b, bh[e][ct], bl[e][ct]);
           }
+        if constexpr (PRIO) __builtin_amdgcn_s_setprio(1);
 #pragma unroll
         for (int e = 0; e < EW; ++e)
 #pragma unroll
@@ -350,6 +351,7 @@ __device__ __forceinline__ void split_item(const SplitArgs& sa, const uint4* __r
           for (int ct = 0; ct < NT; ++ct)
 #pragma unroll
             for (int dt = 0; dt < NT; ++dt) acc2[e][dt][ct] = P::mma(gl[dt], bh[e][ct], acc2[e][dt][ct]);
+        if constexpr (PRIO) __builtin_amdgcn_s_setprio(0);
       }
 
       // shift-window epilogue per CTF set of the group (FP32; the FP64
