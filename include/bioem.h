@@ -130,7 +130,9 @@ const char* bioem_version(void);
  *           the handle: it also sets the CTF frequency scale in bioem_logpost).
  * Each projection is I0[k][j] = sum_a w_a Ey_a[k] Ex_a[j] with pixel-box
  * integrals of the rotated Gaussians (FP64), then its half-spectrum DFT,
- * stored on the device.  *out must be released with bioem_free_proj. */
+ * stored on the device twice: column-major, and in the matrix-fragment order
+ * that the split-precision posterior reads (about 2 x 8 (nx/2+1) ny bytes per
+ * projection in all).  *out must be released with bioem_free_proj. */
 bioem_status bioem_project(bioem_ctx* ctx, const double* spheres, int32_t ns,
                            const double* quats, int32_t nq, int32_t nx, int32_t ny,
                            double pixel_A, bioem_mem in_mem, bioem_proj** out);
@@ -138,8 +140,8 @@ bioem_status bioem_project(bioem_ctx* ctx, const double* spheres, int32_t ns,
 /* Observed images (Section 3: the spectra and per-image sums C_o, C_oo are
  * precalculated).  imgs is [ni][ny][nx] float32.  Computes, in FP64 from the
  * pixels, C_o = sum I, C_oo = sum I^2 and A = sum (I - C_o/n)^2, and the
- * half-spectrum DFT of each image.  *out must be released with
- * bioem_free_imgs. */
+ * half-spectrum DFT of each image (stored twice, as for bioem_project).
+ * *out must be released with bioem_free_imgs. */
 bioem_status bioem_prepare_images(bioem_ctx* ctx, const float* imgs, int32_t ni, int32_t nx,
                                   int32_t ny, bioem_mem in_mem, bioem_imgs** out);
 
