@@ -10,8 +10,8 @@ namespace bioem {
 
 namespace {
 
-constexpr int kProjWaves = 4;      // waves per projection workgroup (one per SIMD)
-constexpr int kProjTiles = 25;     // 16x16 output tiles per wave
+constexpr int kProjWaves = 8;      // waves per projection workgroup (two per SIMD)
+constexpr int kProjTiles = 13;     // 16x16 output tiles per wave
 constexpr int kProjChunk = 8;      // spheres per LDS stage (two MFMA K-steps)
 constexpr int kProjSeg = 63;       // pixels per wave segment (64 boundaries)
 constexpr int kProjSuper = 2048;   // spheres whose rotated parameters sit in LDS at once
