@@ -15,6 +15,8 @@ constexpr int kProjTiles = 13;     // 16x16 output tiles per wave
 constexpr int kProjChunk = 8;      // spheres per LDS stage (two MFMA K-steps)
 constexpr int kProjSeg = 63;       // pixels per wave segment (64 boundaries)
 constexpr int kProjSuper = 2048;   // spheres whose rotated parameters sit in LDS at once
+constexpr int kDftRows = 8;        // rows per workgroup of the forward row transform
+constexpr int kDftCols = 4;        // columns per workgroup of the forward column transform
 
 typedef double d4 __attribute__((ext_vector_type(4)));
 
@@ -173,57 +175,79 @@ __global__ __launch_bounds__(64 * kProjWaves, 1) void k_project(const double* __
 }
 
 // Row pass of the forward 2-D DFT: rows[i][k][m] = sum_j x[i][k][j] e^{-2 pi i m j / nx}.
-// grid: n * ny blocks; block: 128.
+// grid: ceil(n * ny / kDftRows) blocks; block: 128.
 __global__ __launch_bounds__(128) void k_rdft_rows(const double* __restrict__ in64,
-                                                   const float* __restrict__ in32, int nx,
+                                                   const float* __restrict__ in32, int nx, long nrows,
                                                    double2* __restrict__ rows) {
-  __shared__ double x[kMaxBox];
+  // kDftRows rows per workgroup share each twiddle read; every output is
+  // still one FMA chain over j in increasing order
+  __shared__ double x[kDftRows][kMaxBox];
   __shared__ double2 tw[kMaxBox];
-  const size_t row = blockIdx.x;
+  const long row0 = (long)blockIdx.x * kDftRows;
   const int mh = nx / 2 + 1;
-  for (int j = threadIdx.x; j < nx; j += blockDim.x) {
-    x[j] = in64 ? in64[row * nx + j] : (double)in32[row * nx + j];
-    tw[j] = twiddle64(j, nx);
+  for (int e = threadIdx.x; e < kDftRows * nx; e += blockDim.x) {
+    const int r = e / nx, j = e - r * nx;
+    const long row = row0 + r;
+    x[r][j] = row < nrows ? (in64 ? in64[row * nx + j] : (double)in32[row * nx + j]) : 0.0;
   }
+  for (int j = threadIdx.x; j < nx; j += blockDim.x) tw[j] = twiddle64(j, nx);
   __syncthreads();
   for (int m = threadIdx.x; m < mh; m += blockDim.x) {
-    double re = 0.0, im = 0.0;
+    double re[kDftRows], im[kDftRows];
+#pragma unroll
+    for (int r = 0; r < kDftRows; ++r) re[r] = im[r] = 0.0;
     int t = 0;
     for (int j = 0; j < nx; ++j) {
-      re = fma(x[j], tw[t].x, re);
-      im = fma(-x[j], tw[t].y, im);
+      const double2 w = tw[t];
+#pragma unroll
+      for (int r = 0; r < kDftRows; ++r) {
+        re[r] = fma(x[r][j], w.x, re[r]);
+        im[r] = fma(-x[r][j], w.y, im[r]);
+      }
       t += m;
       if (t >= nx) t -= nx;
     }
-    rows[row * mh + m] = make_double2(re, im);
+#pragma unroll
+    for (int r = 0; r < kDftRows; ++r)
+      if (row0 + r < nrows) rows[(row0 + r) * mh + m] = make_double2(re[r], im[r]);
   }
 }
 
 // Column pass: spec[i][m][l] = sum_k rows[i][k][m] e^{-2 pi i l k / ny}.
-// grid: n * mh blocks; block: 128.
-__global__ __launch_bounds__(128) void k_cdft_cols(const double2* __restrict__ rows, int nx, int ny,
+// grid: n * ceil(mh / kDftCols) blocks (kDftCols columns of one item each);
+// block: 256.
+__global__ __launch_bounds__(256) void k_cdft_cols(const double2* __restrict__ rows, int nx, int ny,
                                                    double2* __restrict__ spec) {
-  __shared__ double2 col[kMaxBox];
+  __shared__ double2 col[kDftCols][kMaxBox];
   __shared__ double2 tw[kMaxBox];
-  const int mh = nx / 2 + 1;
-  const size_t item = blockIdx.x / mh;
-  const int m = blockIdx.x - item * mh;
-  for (int k = threadIdx.x; k < ny; k += blockDim.x) {
-    col[k] = rows[(item * ny + k) * mh + m];
-    tw[k] = twiddle64(k, ny);
+  const int mh = nx / 2 + 1, groups = (mh + kDftCols - 1) / kDftCols;
+  const size_t item = blockIdx.x / groups;
+  const int m0 = (blockIdx.x - (int)item * groups) * kDftCols;
+  for (int e = threadIdx.x; e < kDftCols * ny; e += blockDim.x) {
+    const int c = e / ny, k = e - c * ny;
+    col[c][k] = m0 + c < mh ? rows[(item * ny + k) * mh + m0 + c] : make_double2(0.0, 0.0);
   }
+  for (int k = threadIdx.x; k < ny; k += blockDim.x) tw[k] = twiddle64(k, ny);
   __syncthreads();
   for (int l = threadIdx.x; l < ny; l += blockDim.x) {
-    double re = 0.0, im = 0.0;
+    double re[kDftCols], im[kDftCols];
+#pragma unroll
+    for (int c = 0; c < kDftCols; ++c) re[c] = im[c] = 0.0;
     int t = 0;
     for (int k = 0; k < ny; ++k) {
-      // (a + ib)(c - is) = (ac + bs) + i(bc - as)
-      re = fma(col[k].x, tw[t].x, fma(col[k].y, tw[t].y, re));
-      im = fma(col[k].y, tw[t].x, fma(-col[k].x, tw[t].y, im));
+      const double2 w = tw[t];
+#pragma unroll
+      for (int c = 0; c < kDftCols; ++c) {
+        // (a + ib)(c - is) = (ac + bs) + i(bc - as)
+        re[c] = fma(col[c][k].x, w.x, fma(col[c][k].y, w.y, re[c]));
+        im[c] = fma(col[c][k].y, w.x, fma(-col[c][k].x, w.y, im[c]));
+      }
       t += l;
       if (t >= ny) t -= ny;
     }
-    spec[(item * mh + m) * ny + l] = make_double2(re, im);
+#pragma unroll
+    for (int c = 0; c < kDftCols; ++c)
+      if (m0 + c < mh) spec[(item * mh + m0 + c) * ny + l] = make_double2(re[c], im[c]);
   }
 }
 
@@ -489,8 +513,11 @@ hipError_t launch_project_images(hipStream_t s, const double* spheres, int ns, c
 hipError_t launch_rdft2(hipStream_t s, const double* real_in, const float* real_in_f32, int n,
                         int nx, int ny, double2* rows_scratch, double2* spec64) {
   const int mh = nx / 2 + 1;
-  hipLaunchKernelGGL(k_rdft_rows, dim3(n * ny), dim3(128), 0, s, real_in, real_in_f32, nx, rows_scratch);
-  hipLaunchKernelGGL(k_cdft_cols, dim3(n * mh), dim3(128), 0, s, rows_scratch, nx, ny, spec64);
+  const long nrows = (long)n * ny;
+  hipLaunchKernelGGL(k_rdft_rows, dim3((unsigned)((nrows + kDftRows - 1) / kDftRows)), dim3(128), 0, s, real_in,
+                     real_in_f32, nx, nrows, rows_scratch);
+  hipLaunchKernelGGL(k_cdft_cols, dim3(n * ((mh + kDftCols - 1) / kDftCols)), dim3(256), 0, s, rows_scratch, nx, ny,
+                     spec64);
   return last();
 }
 
