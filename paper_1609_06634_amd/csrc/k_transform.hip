@@ -12,9 +12,9 @@ namespace {
 
 constexpr int kProjWaves = 8;      // waves per projection workgroup (two per SIMD)
 constexpr int kProjTiles = 13;     // 16x16 output tiles per wave
-constexpr int kProjChunk = 8;      // spheres per LDS stage (two MFMA K-steps)
+constexpr int kProjChunk = 16;     // spheres per LDS stage (four MFMA K-steps)
 constexpr int kProjSeg = 63;       // pixels per wave segment (64 boundaries)
-constexpr int kProjSuper = 2048;   // spheres whose rotated parameters sit in LDS at once
+constexpr int kProjSuper = 512;    // spheres whose rotated parameters sit in LDS at once
 constexpr int kDftRows = 8;        // rows per workgroup of the forward row transform
 constexpr int kDftCols = 4;        // columns per workgroup of the forward column transform
 
