@@ -188,7 +188,7 @@ struct SplitCfg {
 };
 
 constexpr int kTuneEW[] = {2, 4};   // the first is the default
-constexpr int kTuneTiles[][2] = {{16, 128}, {8, 256}, {32, 64}, {4, 512}};   // the first is the default
+constexpr int kTuneTiles[][2] = {{32, 128}, {16, 128}, {64, 64}, {8, 256}};   // the first is the default
 
 int ilog2(int v) {
   int r = 0;
@@ -245,6 +245,14 @@ bioem_status split_cfg(bioem_ctx* ctx, const Job& J, int prec, SplitCfg& cfg) {
   cfg = SplitCfg{split_shape_for(bf16), 2, 0, 0};
   if (std::getenv("BIOEM_SPLIT_SHAPE") || !ctx->autotune) {
     cfg.ew = split_shape_ew(cfg.shape);
+    // BIOEM_SPLIT_TILE=IxS overrides the item tile (images x orientation slots)
+    if (const char* t = std::getenv("BIOEM_SPLIT_TILE")) {
+      int ti = 0, ts = 0;
+      if (std::sscanf(t, "%dx%d", &ti, &ts) == 2 && ti > 0 && ts > 0 && ti <= 4096 && ts <= 65536) {
+        cfg.ti = ti;
+        cfg.ts = ts;
+      }
+    }
     return BIOEM_OK;
   }
   const int lq = ilog2(J.nq);

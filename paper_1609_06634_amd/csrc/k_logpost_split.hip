@@ -54,7 +54,7 @@ namespace bioem {
 
 namespace {
 
-constexpr int kTileImages = 16;     // default item tile (images x slots) for cache reuse
+constexpr int kTileImages = 32;     // default item tile (images x slots) for cache reuse
 constexpr int kTileSlots = 128;
 
 using namespace split;
