@@ -136,6 +136,8 @@ def main() -> int:
     ap.add_argument("--epochs", type=int, default=4)
     ap.add_argument("--topk", type=int, default=256)
     ap.add_argument("--tau", type=float, default=0.5)
+    ap.add_argument("--plain-images", type=int, default=8,
+                    help="proposal workload: images scored by the plain FP32 form for comparison")
     ap.add_argument("--no-autotune", action="store_true",
                     help="mixed workload: default launch shape and item tiles for every job")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
@@ -144,7 +146,7 @@ def main() -> int:
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
+        print("bench.py measures one GPU only: the library has no multi-GPU path "
               "(sharding over orientations or images is described in the design notes)",
               file=sys.stderr)
         return 2
@@ -409,10 +411,28 @@ def run_proposal(args, P, ctx, torch, dev) -> int:
     # the proposal alone (no fallback): what the network's top-K captures
     r0 = PR.score_with_proposal(ctx, net, proj, imgs, ctf, S, K=args.topk, tau=0.0, prec=args.prec)
     d0 = ref - r0.logp
+    # the plain form (FP32 transforms, exhaustive grid) on the first images:
+    # the posterior rate the proposal form is compared with, and its log P
+    npl = min(args.plain_images, held_n)
+    im_pl = P.prepare_images(ctx, imgs[:npl].contiguous())
+    P.logpost(ctx, proj, im_pl, ctf, S, prec="f32", device_out=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    plain = P.logpost(ctx, proj, im_pl, ctf, S, prec="f32", device_out=True)["logp"]
+    torch.cuda.synchronize()
+    t_pl = time.perf_counter() - t0
+    im_pl.free()
+    plain_rate = npl * nq * nc / t_pl
+    d_pl = np.abs(r.logp[:npl] - plain.cpu().numpy())
+    log(f"plain FP32 form: {plain_rate:.3g} evals/s on {npl} images; proposal form vs plain max |dlogP| "
+        f"{d_pl.max():.3g}")
     line = {"metric": METRIC + " (effective, learned top-K proposal)", "value": evals / tpr,
             "unit": "evals/s", "n_gpus": 1, "steps": args.steps, "warmup": 1, "ms_per_step": tpr * 1e3,
             "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-            "dtype": "bf16 network; f16x2 split posterior on MFMA (f32 acc), f64 likelihood",
+            "dtype": "bf16 network; " + {"f32": "f32 posterior transforms",
+                                          "split_f16": "f16x2 split posterior on MFMA (f32 acc)",
+                                          "split_bf16": "bf16x2 split posterior on MFMA (f32 acc)"}[args.prec]
+                     + ", f64 likelihood",
             "data": "synthetic",
             "config": {"workload": f"128x128 px at 2.31 A/px, 1000-sphere model, {held_n} held-out images x "
                                    f"{nq} orientations x {nc} CTF sets, shifts +-{S}; top-{args.topk} "
@@ -428,6 +448,8 @@ def run_proposal(args, P, ctx, torch, dev) -> int:
                             "network_mass_median": float(np.median(r0.mass)),
                             "ms_per_step": r0.seconds * 1e3},
             "evals_computed_fraction": r.evals / evals,
+            "plain_f32": {"value": plain_rate, "images": npl, "speedup_of_proposal_form": (evals / tpr) / plain_rate,
+                          "dlogp_max_vs_proposal_form": float(d_pl.max())},
             "training": {"images": args.train_images, "epochs": args.epochs, "seconds": t_train,
                          "label_seconds": label_s, "loss_per_epoch": losses,
                          "label_mass_top32_median": label_mass}}

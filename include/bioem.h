@@ -64,7 +64,7 @@ typedef enum {
   BIOEM_EINVAL = -1,        /* invalid argument (sizes, ranges, non-finite values) */
   BIOEM_ENOMEM = -2,        /* device allocation failed */
   BIOEM_EDEVICE = -3,       /* HIP runtime error or kernel fault */
-  BIOEM_EUNSUPPORTED = -4   /* valid but outside what this build supports */
+  BIOEM_EUNSUPPORTED = -4   /* valid but outside what the library supports */
 } bioem_status;
 
 typedef enum { BIOEM_MEM_HOST = 0, BIOEM_MEM_DEVICE = 1 } bioem_mem;
