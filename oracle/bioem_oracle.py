@@ -213,6 +213,43 @@ def logsumexp_exact(values) -> float:
     return m + math.log(math.fsum(np.exp(v - m)))
 
 
+def ensemble_logpost(logp: np.ndarray, w: Sequence[float]):
+    """Log posterior of a model ensemble, Eq. (pb2) of Section 2.
+
+    ``logp[m][i]`` is the log posterior of image i under model m (as returned
+    by ``logpost_oracle``), ``w[m]`` the ensemble's relative weights (w >= 0,
+    summing to 1).  Per image the ensemble's posterior is the weighted sum
+    over models, ln sum_m w_m exp(logp[m][i]); the images are independent, so
+    the ensemble's log posterior over the whole set is the sum of those over
+    images (the log of the product in Eq. pb2, up to the same constant).
+    Models with w_m = 0 take no part; a NaN among the others gives NaN; an
+    infinite maximum is returned as it is.  Returns (per_image [ni], total).
+    """
+    L = np.asarray(logp, dtype=np.float64)
+    w = np.asarray(w, dtype=np.float64)
+    nm, ni = L.shape
+    per = np.empty(ni)
+    for i in range(ni):
+        terms = [(float(w[m]), float(L[m, i])) for m in range(nm) if w[m] > 0.0]
+        vals = [v for _, v in terms]
+        if any(math.isnan(v) for v in vals):
+            per[i] = math.nan
+            continue
+        M = max(vals)
+        if math.isinf(M):
+            per[i] = M
+            continue
+        per[i] = M + math.log(math.fsum(wm * math.exp(v - M) for wm, v in terms))
+    if ni == 0:
+        return per, 0.0
+    if np.all(np.isfinite(per)):
+        return per, math.fsum(per)
+    # IEEE rules for the infinities: both signs (or a NaN) give NaN
+    if np.any(np.isnan(per)) or (np.any(per == math.inf) and np.any(per == -math.inf)):
+        return per, math.nan
+    return per, math.inf if np.any(per == math.inf) else -math.inf
+
+
 # ---------------------------------------------------------------------------
 # Posterior over the grid (Eq. Pmom; Listing 1's loop nest)
 # ---------------------------------------------------------------------------
