@@ -328,6 +328,30 @@ def run_mixed(args, P, ctx, torch, dev) -> int:
         log(f"{mode}: {evals / dt:.4g} evals/s, kernel {kms / args.steps:.1f} ms per step")
     p, q = res["persistent"], res["per_job"]
     achieved = fp_equiv / (p["kms"] * 1e-3) / 1e12
+    # ensemble posterior, Eq. (pb2), of the two models over every image (each
+    # class holds images of both): its log posterior on a grid of weights,
+    # whose maximum estimates the mixing fraction, and how often the
+    # generating model has the larger per-image posterior
+    L = torch.stack([torch.cat([outs[2 * c + m]["logp"] for c in range(len(classes))])
+                     for m in range(2)]).contiguous()
+    truth = np.concatenate([c["cls"].img_model for c in classes])
+    grid = np.linspace(0.0, 1.0, 21)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    totals = [P.ensemble(ctx, L, [w0, 1.0 - w0], device_out=True)[1] for w0 in grid]
+    torch.cuda.synchronize()
+    t_ens = (time.perf_counter() - t0) / len(grid)
+    totals = np.array([float(t.item()) for t in totals])
+    Lh = L.cpu().numpy()
+    wins = float(np.mean(Lh[truth, np.arange(len(truth))] > Lh[1 - truth, np.arange(len(truth))]))
+    ens = {"images": int(len(truth)), "weight_grid": len(grid),
+           "best_weight_model0": float(grid[int(np.argmax(totals))]),
+           "true_fraction_model0": float(np.mean(truth == 0)),
+           "log_posterior_at_best": float(totals.max()),
+           "log_bayes_factor_model0_over_model1": float(totals[-1] - totals[0]),
+           "generating_model_wins": wins, "ms_per_call": t_ens * 1e3}
+    log(f"ensemble: best w0 {ens['best_weight_model0']:.2f} (true {ens['true_fraction_model0']:.2f}), "
+        f"generating model wins {wins:.3f}, {t_ens * 1e3:.3f} ms per call")
     line = {"metric": METRIC, "value": evals / p["dt"], "unit": "evals/s", "n_gpus": 1,
             "steps": args.steps, "warmup": args.warmup, "ms_per_step": p["dt"] * 1e3,
             "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
@@ -348,6 +372,7 @@ def run_mixed(args, P, ctx, torch, dev) -> int:
             "per_job": {"value": evals / q["dt"], "ms_per_step": q["dt"] * 1e3,
                         "kernel_ms_per_step": q["kms"], "launches_per_step": q["launches"]},
             "persistent_over_per_job": q["dt"] / p["dt"],
+            "ensemble": ens,
             "tuning": ctx.tunings()}
     print(json.dumps(line), flush=True)
     ctx.close()

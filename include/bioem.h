@@ -309,6 +309,29 @@ bioem_status bioem_render(bioem_ctx* ctx, const bioem_proj* proj, const double* 
 bioem_status bioem_set_timing(bioem_ctx* ctx, int32_t enable);
 bioem_status bioem_get_kernel_time(bioem_ctx* ctx, double* ms, int32_t* launches, double* evals);
 
+/* Posterior of a model ensemble, Eq. (pb2) of Section 2: models m = 0..nm-1
+ * with relative weights w_m (w_m >= 0, summing to 1 within 1e-9) and the
+ * per-image log posteriors logp[m][i] that bioem_logpost returns for each
+ * model on the same ni images (same grid sizes, so the priors match):
+ *   per_image[i] = ln sum_m w_m exp(logp[m][i]),
+ *   total        = sum_i per_image[i],
+ * the log of Eq. (pb2)'s product over independent images (up to the same
+ * constant as the per-model values).  With one weight equal to 1, total is
+ * that model's log evidence over the set; differences of such totals are log
+ * Bayes factors between models.  FP64; the largest weighted term is taken
+ * out before the exponentials; total is summed in a fixed order
+ * (deterministic).  Models with w_m = 0 take no part (also when their logp
+ * is NaN, e.g. a degenerate image); a NaN among the others makes that image's
+ * value NaN, and total follows IEEE rules (NaN, or +-inf).
+ *   logp [nm][ni] float64, host or device per in_mem (may be NULL if ni = 0);
+ *   w [nm] float64, always host memory;
+ *   per_image [ni] (NULL to skip) and total [1] float64 per out_mem.
+ * ni = 0 gives total = 0.  Returns after the results are written.
+ * EINVAL: nm < 1, ni < 0, a NULL array that is needed, a bad memory kind, a
+ * negative or non-finite weight, weights not summing to 1. */
+bioem_status bioem_ensemble(bioem_ctx* ctx, const double* logp, int32_t nm, int32_t ni, int32_t in_mem,
+                            const double* w, double* per_image, double* total, int32_t out_mem);
+
 void bioem_free_proj(bioem_proj* p);
 void bioem_free_imgs(bioem_imgs* p);
 

@@ -106,6 +106,7 @@ SIGNATURES = [
     ("bioem_cnn_adam", _I, [_P, _P, ctypes.c_float, ctypes.c_float, ctypes.c_float, ctypes.c_float]),
     ("bioem_cnn_propose", _I, [_P, _P, _P, _I, _I, _I, _P, _P, _I]),
     ("bioem_topk", _I, [_P, _P, _I, _I, _I, _I, _P, _P, _I]),
+    ("bioem_ensemble", _I, [_P, _P, _I, _I, _I, _P, _P, _P, _I]),
     ("bioem_cnn_input", _I, [_P, _P, _I, _I, _I, _I, _P, _I]),
 ]
 
@@ -368,6 +369,31 @@ def topk(ctx: Context, z, K: int, device_out: bool = False):
     mass = np.empty(B, np.float32)
     ctx.check(ctx._lib.bioem_topk(ctx.h, zp, B, n, K, m, idx.ctypes.data, mass.ctypes.data, MEM_HOST))
     return idx, mass
+
+
+def ensemble(ctx: Context, logp, w, device_out: bool = False):
+    """(per_image [ni], total) of the ensemble posterior, Eq. (pb2): logp
+    [nm][ni] per-model log posteriors (numpy or CUDA tensor), w [nm] weights."""
+    lp, m, keep = _arg(logp, np.float64)
+    if keep.ndim != 2:
+        raise ValueError("logp must be [nm][ni]")
+    nm, ni = (int(v) for v in keep.shape)
+    wa = np.ascontiguousarray(w, dtype=np.float64)
+    if wa.shape != (nm,):
+        raise ValueError(f"expected {nm} weights, got shape {wa.shape}")
+    if device_out:
+        torch = _torch()
+        dev = torch.device("cuda", ctx.device)
+        per = torch.empty(ni, dtype=torch.float64, device=dev)
+        tot = torch.empty(1, dtype=torch.float64, device=dev)
+        ctx.check(ctx._lib.bioem_ensemble(ctx.h, lp, nm, ni, m, wa.ctypes.data, per.data_ptr(), tot.data_ptr(),
+                                          MEM_DEVICE))
+        return per, tot
+    per = np.empty(ni, np.float64)
+    tot = np.empty(1, np.float64)
+    ctx.check(ctx._lib.bioem_ensemble(ctx.h, lp, nm, ni, m, wa.ctypes.data, per.ctypes.data, tot.ctypes.data,
+                                      MEM_HOST))
+    return per, float(tot[0])
 
 
 class Net:

@@ -723,4 +723,43 @@ bioem_status bioem_tuning_entry(const bioem_ctx* ctx, int32_t idx, bioem_tuning*
   return BIOEM_OK;
 }
 
+bioem_status bioem_ensemble(bioem_ctx* ctx, const double* logp, int32_t nm, int32_t ni, int32_t in_mem,
+                            const double* w, double* per_image, double* total, int32_t out_mem) {
+  if (!ctx) return BIOEM_EINVAL;
+  if (!w || !total || nm < 1 || ni < 0 || (ni > 0 && !logp) || !valid_mem(in_mem) || !valid_mem(out_mem))
+    return fail(ctx, BIOEM_EINVAL, "bioem_ensemble: bad argument");
+  double wsum = 0.0;
+  for (int m = 0; m < nm; ++m) {
+    if (!std::isfinite(w[m]) || w[m] < 0.0)
+      return fail(ctx, BIOEM_EINVAL, "bioem_ensemble: weight %d is negative or not finite", m);
+    wsum += w[m];
+  }
+  if (!(std::fabs(wsum - 1.0) <= 1e-9))
+    return fail(ctx, BIOEM_EINVAL, "bioem_ensemble: weights sum to %.17g, not 1", wsum);
+  HIP_OR_FAIL(ctx, hipSetDevice(ctx->device));
+  hipStream_t s = ctx->stream;
+  DevIn dl, dw;
+  HIP_OR_FAIL(ctx, dl.set(ni > 0 ? logp : nullptr, sizeof(double) * (size_t)nm * ni, (bioem_mem)in_mem, s));
+  HIP_OR_FAIL(ctx, dw.set(w, sizeof(double) * (size_t)nm, BIOEM_MEM_HOST, s));
+  DevMem dper, dtot;
+  double* per = per_image;
+  double* tot = total;
+  if (out_mem == BIOEM_MEM_HOST || !per_image) {
+    HIP_OR_FAIL(ctx, dper.alloc(sizeof(double) * (size_t)ni));
+    per = dper.as<double>();
+  }
+  if (out_mem == BIOEM_MEM_HOST) {
+    HIP_OR_FAIL(ctx, dtot.alloc(sizeof(double)));
+    tot = dtot.as<double>();
+  }
+  HIP_OR_FAIL(ctx, launch_ensemble(s, dl.as<double>(), nm, ni, dw.as<double>(), per, tot));
+  if (out_mem == BIOEM_MEM_HOST) {
+    if (per_image && ni > 0)
+      HIP_OR_FAIL(ctx, hipMemcpyAsync(per_image, per, sizeof(double) * (size_t)ni, hipMemcpyDeviceToHost, s));
+    HIP_OR_FAIL(ctx, hipMemcpyAsync(total, tot, sizeof(double), hipMemcpyDeviceToHost, s));
+  }
+  HIP_OR_FAIL(ctx, hipStreamSynchronize(s));
+  return BIOEM_OK;
+}
+
 }  // extern "C"

@@ -146,6 +146,11 @@ struct FinalizeArgs {
 };
 hipError_t launch_finalize(hipStream_t s, const FinalizeArgs& f);
 
+// Ensemble posterior over models (weights w [nm], device): per [ni] and
+// total [1] from logp [nm][ni]; per may only be null when ni == 0.
+hipError_t launch_ensemble(hipStream_t s, const double* logp, int nm, int ni, const double* w, double* per,
+                           double* total);
+
 }  // namespace bioem
 
 // ---- device helpers ---------------------------------------------------------
