@@ -176,6 +176,36 @@ def correlation_fft(img: np.ndarray, i1: np.ndarray, S: int) -> np.ndarray:
     return out[0] if single else out
 
 
+def correlation_cropped(img: np.ndarray, i1: np.ndarray, S: int):
+    """Real-space variant of Section 3 (Center displacement) with cropping.
+
+    The calculated image moved by d is I1(r + d) where r + d lies in the box
+    and 0 elsewhere: pixels moved out of the box are lost and none wrap in
+    (the paper contrasts this cropping with the wrap of the Fourier variant).
+    Returns (X, B): X[i][dy+S][dx+S] = sum_r (I_o(r) - mean) I1_d(r), the
+    centred cross-correlation, and B[dy+S][dx+S] = sum_r (I1_d(r) - mean)^2
+    over the whole box, which now depends on d (two-pass sums).
+    """
+    imgs = np.asarray(img, dtype=np.float64)
+    single = imgs.ndim == 2
+    if single:
+        imgs = imgs[None]
+    ni, ny, nx = imgs.shape
+    ic = (imgs - imgs.reshape(ni, -1).mean(axis=1)[:, None, None]).reshape(ni, -1)
+    p = np.asarray(i1, dtype=np.float64)
+    w = 2 * S + 1
+    X = np.empty((ni, w, w))
+    B = np.empty((w, w))
+    for dy in range(-S, S + 1):
+        for dx in range(-S, S + 1):
+            moved = np.zeros_like(p)
+            moved[max(0, -dy):ny - max(0, dy), max(0, -dx):nx - max(0, dx)] = \
+                p[max(0, dy):ny + min(0, dy), max(0, dx):nx + min(0, dx)]
+            X[:, dy + S, dx + S] = ic @ moved.ravel()
+            B[dy + S, dx + S] = projection_norm(moved)
+    return (X[0] if single else X), B
+
+
 # ---------------------------------------------------------------------------
 # Marginal likelihood (Section 2, Eq. likeli; Section 3, analytic integration)
 # ---------------------------------------------------------------------------
@@ -268,7 +298,7 @@ class OracleResult:
 
 def logpost_oracle(images: np.ndarray, spheres: np.ndarray, quats: np.ndarray,
                    ctfs: np.ndarray, pixel: float, S: int, method: str = "direct",
-                   q_subset: Optional[Sequence[int]] = None) -> OracleResult:
+                   q_subset: Optional[Sequence[int]] = None, borders: str = "wrap") -> OracleResult:
     """log P_{m,omega} for every image over the orientation x CTF x shift grid.
 
     P is the integral of Eq. (Pmom) with mu, N and lambda integrated
@@ -280,6 +310,8 @@ def logpost_oracle(images: np.ndarray, spheres: np.ndarray, quats: np.ndarray,
     maximising grid point (ties go to the lowest (q, c, dy, dx)) and the
     posterior restricted to each orientation (LSE over c and d).
     ``q_subset`` evaluates only those orientations (the prior keeps Nq).
+    ``borders="crop"`` takes the real-space variant with cropping
+    (``correlation_cropped``: B depends on d) instead of the wrap.
     """
     imgs = np.asarray(images, dtype=np.float64)
     ni, ny, nx = imgs.shape
@@ -287,6 +319,8 @@ def logpost_oracle(images: np.ndarray, spheres: np.ndarray, quats: np.ndarray,
     nq, nc = len(quats), len(ctfs)
     nd = (2 * S + 1) ** 2
     corr = {"direct": correlation_direct, "fft": correlation_fft}[method]
+    if borders not in ("wrap", "crop"):
+        raise ValueError(f"borders must be 'wrap' or 'crop', not {borders!r}")
     A = np.array([image_moments(im)[2] for im in imgs])
     tables = [ctf_envelope_table(a, amp, b, nx, ny, pixel) for a, amp, b in ctfs]
     qs = range(nq) if q_subset is None else q_subset
@@ -302,6 +336,13 @@ def logpost_oracle(images: np.ndarray, spheres: np.ndarray, quats: np.ndarray,
         per_c = np.empty((ni, nc, 2 * S + 1, 2 * S + 1))
         for c in range(nc):
             i1 = filtered_projection(i0, tables[c])
+            if borders == "crop":
+                X, Bd = correlation_cropped(imgs, i1, S)
+                for i in range(ni):
+                    for dy in range(2 * S + 1):
+                        for dx in range(2 * S + 1):
+                            per_c[i, c, dy, dx] = log_likelihood(X[i, dy, dx], A[i], Bd[dy, dx], n)
+                continue
             B = projection_norm(i1)
             X = corr(imgs, i1, S)
             for i in range(ni):
