@@ -128,7 +128,7 @@ def main() -> int:
     ap.add_argument("--images", type=int, default=1000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", default="2x8x2")
-    ap.add_argument("--workload", default="paper224", choices=["paper224", "mixed", "proposal"],
+    ap.add_argument("--workload", default="paper224", choices=["paper224", "mixed", "proposal", "crossover"],
                     help="paper224: 224^2, 1000 images x 4608 orientations x 8 CTF sets (default); "
                          "mixed: 96/128/180/224 px classes x two models in one persistent launch; "
                          "proposal: 128^2 x 36,864 orientations with the learned top-K proposal")
@@ -172,6 +172,8 @@ def main() -> int:
         return run_mixed(args, P, ctx, torch, dev)
     if args.workload == "proposal":
         return run_proposal(args, P, ctx, torch, dev)
+    if args.workload == "crossover":
+        return run_crossover(args, P, ctx, torch, dev)
 
     # ---- inputs, resident in HBM ------------------------------------------------
     log("generating the 224^2 workload")
@@ -248,6 +250,70 @@ def main() -> int:
     if not args.no_cpu_baseline:
         log(f"timing the CPU oracle on a {args.cpu_sample} sample")
         line["cpu_baseline"] = cpu_baseline(args.cpu_sample)
+    print(json.dumps(line), flush=True)
+    ctx.close()
+    return 0
+
+
+def run_crossover(args, P, ctx, torch, dev) -> int:
+    """Real-space (direct, border-cropping) against Fourier (wrapping) forms of
+    the displacement sum as the window grows (S = 0..3): whole-call time per
+    form on the 224^2 workload's full orientation x CTF grid, for a subset of
+    its images.  Fourier calls include bioem_prepare_images; the real-space
+    call includes making its nq x nc calculated images."""
+    import numpy as np
+    from workloads import make_workload
+    ni = args.images if args.images != 1000 else 100
+    log(f"generating the 224^2 workload ({ni} images)")
+    wl = make_workload(2, n_images=ni)
+    cls = wl.classes[0]
+    model = torch.from_numpy(wl.models[0]).to(dev)
+    pr = P.project(ctx, model, torch.from_numpy(cls.img_quat).to(dev), cls.nx, cls.ny, cls.pixel_A)
+    imgs = P.render(ctx, pr, torch.from_numpy(cls.img_ctf).to(dev), torch.from_numpy(cls.img_shift).to(dev),
+                    noise=torch.from_numpy(cls.noise(0, ni)).to(dev), snr=cls.snr, device_out=True)
+    pr.free()
+    ctf = torch.from_numpy(cls.ctf).to(dev)
+    proj = P.project(ctx, model, torch.from_numpy(cls.quats).to(dev), cls.nx, cls.ny, cls.pixel_A)
+    nq, nc = len(cls.quats), len(cls.ctf)
+    evals = ni * nq * nc
+
+    def fourier(S, prec):
+        im = P.prepare_images(ctx, imgs)
+        o = P.logpost(ctx, proj, im, ctf, S, prec=prec, device_out=True)
+        im.free()
+        return o["logp"]
+
+    def crop(S):
+        return P.logpost_crop(ctx, proj, imgs, ctf, S, device_out=True)["logp"]
+
+    def timed(fn):
+        fn()   # warm
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            out = fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / args.steps, out
+
+    points = []
+    for S in range(4):
+        tc, lc = timed(lambda: crop(S))
+        tf, lf = timed(lambda: fourier(S, "f32"))
+        ts, _ = timed(lambda: fourier(S, "split_f16"))
+        d = float((lc - lf).abs().max())
+        points.append({"S": S, "displacements": (2 * S + 1) ** 2, "crop_ms": tc * 1e3, "fourier_f32_ms": tf * 1e3,
+                       "fourier_split_f16_ms": ts * 1e3, "crop_evals_per_s": evals / tc,
+                       "fourier_f32_evals_per_s": evals / tf, "fourier_split_f16_evals_per_s": evals / ts,
+                       "max_dlogp_crop_vs_wrap": d})
+        log(f"S={S}: crop {tc * 1e3:.1f} ms, Fourier f32 {tf * 1e3:.1f} ms, split f16 {ts * 1e3:.1f} ms, "
+            f"max |log P crop - wrap| {d:.3g}")
+    proj.free()
+    line = {"metric": "posterior evals/s per form vs shift window (real-space crop vs Fourier wrap)",
+            "value": None, "unit": "evals/s", "n_gpus": 1, "steps": args.steps, "higher_is_better": True,
+            "data": "synthetic",
+            "config": {"workload": f"224x224 px at 1.32 A/px, {ni} images x {nq} orientations x {nc} CTF sets, "
+                                   "S = 0..3", "evals_per_call": evals},
+            "points": points}
     print(json.dumps(line), flush=True)
     ctx.close()
     return 0

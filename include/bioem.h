@@ -309,6 +309,30 @@ bioem_status bioem_render(bioem_ctx* ctx, const bioem_proj* proj, const double* 
 bioem_status bioem_set_timing(bioem_ctx* ctx, int32_t enable);
 bioem_status bioem_get_kernel_time(bioem_ctx* ctx, double* ms, int32_t* launches, double* evals);
 
+/* Real-space variant of the displacement sum (Section 3, Center
+ * displacement) with border cropping instead of the Fourier variant's wrap:
+ * the calculated image moved by d keeps I1(r + d) where r + d lies in the
+ * box and is 0 elsewhere, so its centred sum of squares B(d) depends on d;
+ * everything else is as in bioem_logpost (Eq. likeli integrated over offset,
+ * scale and noise; uniform grid priors; FP64 likelihood and sums).  The
+ * correlation is direct, (2S+1)^2 multiply-adds per pixel and evaluation
+ * (FP32 products, FP32 row sums added in FP64), so this form is for small
+ * windows: max_shift <= 3.
+ *   proj: nq projections (bioem_project); imgs [ni][ny][nx] float32 raw
+ *   pixels of the same box (not a bioem_imgs handle: the direct form reads
+ *   pixels), host or device per in_mem; ctf [nc][3] (a, A, b) per in_mem;
+ *   logp [ni] and best [ni] per out_mem (best.logl is the maximal l, ties
+ *   to the lowest (q, c, dy, dx)).
+ * Device memory used: nq*nc calculated images (4 B per pixel) plus records
+ * of at most 1 GiB.  Returns after the results are written.
+ * EINVAL: bad pointers, sizes or memory kinds, max_shift < 0 or
+ * 2*max_shift >= min(nx, ny), non-finite CTF values or A outside [0, 1].
+ * EUNSUPPORTED: max_shift > 3, or a box too wide for the kernel's LDS
+ * staging at that window (16 x (2S+1) rows of nx + 2S floats). */
+bioem_status bioem_logpost_crop(bioem_ctx* ctx, const bioem_proj* proj, const float* imgs, int32_t ni,
+                                int32_t in_mem, const double* ctf, int32_t nc, int32_t max_shift, double* logp,
+                                bioem_best* best, int32_t out_mem);
+
 /* Posterior of a model ensemble, Eq. (pb2) of Section 2: models m = 0..nm-1
  * with relative weights w_m (w_m >= 0, summing to 1 within 1e-9) and the
  * per-image log posteriors logp[m][i] that bioem_logpost returns for each

@@ -5,7 +5,7 @@ builds it and marshals arguments to it.
 """
 from .bindings import (  # noqa: F401
     Context, Projections, Images, BioemError, project, prepare_images, logpost, render,
-    ctf_from_physical, version, load, best_from_bytes, BEST_DTYPE, LIB_PATH, logpost_batch, Net, topk, cnn_input, ensemble,
+    ctf_from_physical, version, load, best_from_bytes, BEST_DTYPE, LIB_PATH, logpost_batch, Net, topk, cnn_input, ensemble, logpost_crop,
 )
 
 

@@ -107,6 +107,7 @@ SIGNATURES = [
     ("bioem_cnn_propose", _I, [_P, _P, _P, _I, _I, _I, _P, _P, _I]),
     ("bioem_topk", _I, [_P, _P, _I, _I, _I, _I, _P, _P, _I]),
     ("bioem_ensemble", _I, [_P, _P, _I, _I, _I, _P, _P, _P, _I]),
+    ("bioem_logpost_crop", _I, [_P, _P, _P, _I, _I, _P, _I, _I, _P, _P, _I]),
     ("bioem_cnn_input", _I, [_P, _P, _I, _I, _I, _I, _P, _I]),
 ]
 
@@ -369,6 +370,33 @@ def topk(ctx: Context, z, K: int, device_out: bool = False):
     mass = np.empty(B, np.float32)
     ctx.check(ctx._lib.bioem_topk(ctx.h, zp, B, n, K, m, idx.ctypes.data, mass.ctypes.data, MEM_HOST))
     return idx, mass
+
+
+def logpost_crop(ctx: Context, proj: Projections, images, ctf, max_shift: int, device_out: bool = False):
+    """Log posterior per image with the real-space, border-cropping form of
+    the displacement sum (direct correlation, max_shift <= 3); images are the
+    raw pixels [ni][ny][nx] (numpy or CUDA tensor)."""
+    ip, im, keep = _arg(images, np.float32)
+    if keep.ndim != 3 or tuple(keep.shape[1:]) != (proj.ny, proj.nx):
+        raise ValueError(f"images must be [ni][{proj.ny}][{proj.nx}]")
+    ni = int(keep.shape[0])
+    cp, cm, ck = _arg(ctf, np.float64)
+    if cm != im:
+        raise ValueError("images and ctf must both be host arrays or both device tensors")
+    nc = int(ck.shape[0])
+    if device_out:
+        torch = _torch()
+        dev = torch.device("cuda", ctx.device)
+        logp = torch.empty(ni, dtype=torch.float64, device=dev)
+        best = torch.empty(ni * BEST_DTYPE.itemsize, dtype=torch.uint8, device=dev)
+        ctx.check(ctx._lib.bioem_logpost_crop(ctx.h, proj.h, ip, ni, im, cp, nc, int(max_shift), logp.data_ptr(),
+                                              best.data_ptr(), MEM_DEVICE))
+        return {"logp": logp, "best": best}
+    logp = np.empty(ni, np.float64)
+    best = np.empty(ni, BEST_DTYPE)
+    ctx.check(ctx._lib.bioem_logpost_crop(ctx.h, proj.h, ip, ni, im, cp, nc, int(max_shift), logp.ctypes.data,
+                                          best.ctypes.data, MEM_HOST))
+    return {"logp": logp, "best": best}
 
 
 def ensemble(ctx: Context, logp, w, device_out: bool = False):

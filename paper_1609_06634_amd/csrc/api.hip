@@ -723,6 +723,93 @@ bioem_status bioem_tuning_entry(const bioem_ctx* ctx, int32_t idx, bioem_tuning*
   return BIOEM_OK;
 }
 
+bioem_status bioem_logpost_crop(bioem_ctx* ctx, const bioem_proj* proj, const float* imgs, int32_t ni,
+                                int32_t in_mem, const double* ctf, int32_t nc, int32_t max_shift, double* logp,
+                                bioem_best* best, int32_t out_mem) {
+  if (!ctx) return BIOEM_EINVAL;
+  if (!proj || !imgs || !ctf || !logp || !best || ni < 1 || nc < 1 || !valid_mem(in_mem) || !valid_mem(out_mem))
+    return fail(ctx, BIOEM_EINVAL, "bioem_logpost_crop: bad argument");
+  const int nx = proj->nx, ny = proj->ny, nq = proj->n, S = max_shift;
+  if (S < 0 || 2 * S >= std::min(nx, ny))
+    return fail(ctx, BIOEM_EINVAL, "bioem_logpost_crop: max_shift %d outside [0, min(nx, ny)/2)", S);
+  if (S > kCropMaxShift || crop_smem_bytes(nx, S) > kMaxSmem)
+    return fail(ctx, BIOEM_EUNSUPPORTED, "bioem_logpost_crop: the direct form takes max_shift <= %d (and "
+                "%zu bytes of LDS at this box)", kCropMaxShift, crop_smem_bytes(nx, S));
+  if ((size_t)nq * nc > (size_t)INT32_MAX / 2)
+    return fail(ctx, BIOEM_EINVAL, "bioem_logpost_crop: too many orientation x CTF pairs");
+  HIP_OR_FAIL(ctx, hipSetDevice(ctx->device));
+  hipStream_t s = ctx->stream;
+  const int np = nq * nc, W = (2 * S + 1) * (2 * S + 1), mh = nx / 2 + 1;
+  const size_t npix = (size_t)nx * ny, len = (size_t)mh * ny, slen = (size_t)mh * spec_ld(ny);
+  std::vector<double> hc;
+  HIP_OR_FAIL(ctx, to_host(ctf, (size_t)nc * 3, (bioem_mem)in_mem, s, hc));
+  if (!finite_all(hc.data(), hc.size())) return fail(ctx, BIOEM_EINVAL, "bioem_logpost_crop: non-finite CTF value");
+  for (int c = 0; c < nc; ++c)
+    if (!(hc[3 * c + 1] >= 0.0 && hc[3 * c + 1] <= 1.0))
+      return fail(ctx, BIOEM_EINVAL, "bioem_logpost_crop: amplitude contrast of set %d outside [0,1]", c);
+  DevIn dimg;
+  HIP_OR_FAIL(ctx, dimg.set(imgs, sizeof(float) * npix * ni, (bioem_mem)in_mem, s));
+  DevMem stats, P, Bd, rec, crep, shifts, dlogp, dbest;
+  HIP_OR_FAIL(ctx, stats.alloc(sizeof(double) * 3 * (size_t)ni));
+  HIP_OR_FAIL(ctx, launch_image_stats(s, dimg.as<float>(), ni, (int)npix, stats.as<double>()));
+  // calculated images I1 = F^-1[F(I0) CTF Env], one per (CTF set, orientation)
+  HIP_OR_FAIL(ctx, P.alloc(sizeof(float) * npix * np));
+  HIP_OR_FAIL(ctx, crep.alloc(sizeof(double) * 3 * (size_t)nq));
+  HIP_OR_FAIL(ctx, shifts.alloc(sizeof(int32_t) * 2 * (size_t)nq));
+  HIP_OR_FAIL(ctx, hipMemsetAsync(shifts.p, 0, sizeof(int32_t) * 2 * (size_t)nq, s));
+  std::vector<double> rep(3 * (size_t)nq);
+  const size_t per = len * 16 + (size_t)ny * mh * 16 + npix * 8;
+  const int chunk = chunk_items(nq, per);
+  DevMem s64, cols, i1;
+  HIP_OR_FAIL(ctx, s64.alloc((size_t)chunk * len * 16));
+  HIP_OR_FAIL(ctx, cols.alloc((size_t)chunk * ny * mh * 16));
+  HIP_OR_FAIL(ctx, i1.alloc((size_t)chunk * npix * 8));
+  for (int c = 0; c < nc; ++c) {
+    for (int q = 0; q < nq; ++q)
+      for (int k = 0; k < 3; ++k) rep[3 * (size_t)q + k] = hc[3 * (size_t)c + k];
+    HIP_OR_FAIL(ctx, hipMemcpyAsync(crep.p, rep.data(), rep.size() * 8, hipMemcpyHostToDevice, s));
+    HIP_OR_FAIL(ctx, hipStreamSynchronize(s));   // rep is rewritten for the next set
+    for (int q0 = 0; q0 < nq; q0 += chunk) {
+      const int cn = std::min(chunk, nq - q0);
+      HIP_OR_FAIL(ctx, launch_render(s, proj->spec + slen * q0, proj->expo + q0, cn, nx, ny, proj->pixel,
+                                     crep.as<double>() + 3 * (size_t)q0, shifts.as<int32_t>() + 2 * (size_t)q0,
+                                     nullptr, nullptr, 1.0, s64.as<double2>(), cols.as<double2>(),
+                                     i1.as<double>(), P.as<float>() + npix * ((size_t)c * nq + q0)));
+    }
+  }
+  HIP_OR_FAIL(ctx, Bd.alloc(sizeof(double) * W * (size_t)np));
+  CropArgs a{};
+  a.p = P.as<float>(); a.np = np; a.nq = nq; a.nx = nx; a.ny = ny; a.S = S; a.Bd = Bd.as<double>();
+  HIP_OR_FAIL(ctx, launch_crop_norms(s, a));
+  // per-evaluation records for a chunk of images at a time
+  const int ci = std::max(1, std::min<int>(ni, (int)std::min<size_t>(kScratchBudget / (sizeof(bioem_crec) * np),
+                                                                      (size_t)INT32_MAX)));
+  HIP_OR_FAIL(ctx, rec.alloc(sizeof(bioem_crec) * (size_t)ci * np));
+  double* lo = logp;
+  bioem_best* bo = best;
+  if (out_mem == BIOEM_MEM_HOST) {
+    HIP_OR_FAIL(ctx, dlogp.alloc(sizeof(double) * ni));
+    HIP_OR_FAIL(ctx, dbest.alloc(sizeof(bioem_best) * ni));
+    lo = dlogp.as<double>();
+    bo = dbest.as<bioem_best>();
+  }
+  const double log_prior = -std::log((double)nq) - std::log((double)nc) - std::log((double)W);
+  for (int i0 = 0; i0 < ni; i0 += ci) {
+    a.imgs = dimg.as<float>() + npix * i0;
+    a.stats = stats.as<double>() + 3 * (size_t)i0;
+    a.ni = std::min(ci, ni - i0);
+    a.rec = rec.as<bioem_crec>();
+    HIP_OR_FAIL(ctx, launch_crop_xcorr(s, a));
+    HIP_OR_FAIL(ctx, launch_crop_finalize(s, a, log_prior, lo + i0, bo + i0));
+  }
+  if (out_mem == BIOEM_MEM_HOST) {
+    HIP_OR_FAIL(ctx, hipMemcpyAsync(logp, lo, sizeof(double) * ni, hipMemcpyDeviceToHost, s));
+    HIP_OR_FAIL(ctx, hipMemcpyAsync(best, bo, sizeof(bioem_best) * ni, hipMemcpyDeviceToHost, s));
+  }
+  HIP_OR_FAIL(ctx, hipStreamSynchronize(s));
+  return BIOEM_OK;
+}
+
 bioem_status bioem_ensemble(bioem_ctx* ctx, const double* logp, int32_t nm, int32_t ni, int32_t in_mem,
                             const double* w, double* per_image, double* total, int32_t out_mem) {
   if (!ctx) return BIOEM_EINVAL;

@@ -146,6 +146,29 @@ struct FinalizeArgs {
 };
 hipError_t launch_finalize(hipStream_t s, const FinalizeArgs& f);
 
+// Real-space variant with border cropping (small windows, S <= kCropMaxShift).
+// Calculated images p [np][ny][nx] float (index = c * nq + q), images
+// [ni][ny][nx] float with stats [ni][3]; Bd [np][W] and rec [ni][np] scratch.
+struct bioem_crec {
+  double lmax;    // window maximum of l(d)
+  double rel;     // sum_d exp(l(d) - lmax), in [1, W]
+  int32_t d;      // (dy+S)*(2S+1) + (dx+S) of the maximum; -1: no valid d
+  int32_t pad;
+};
+constexpr int kCropMaxShift = 3;
+struct CropArgs {
+  const float* imgs; const double* stats; int ni;
+  const float* p; int np, nq;
+  int nx, ny, S;
+  double* Bd;
+  bioem_crec* rec;
+};
+size_t crop_smem_bytes(int nx, int S);
+hipError_t launch_crop_norms(hipStream_t s, const CropArgs& a);
+hipError_t launch_crop_xcorr(hipStream_t s, const CropArgs& a);
+hipError_t launch_crop_finalize(hipStream_t s, const CropArgs& a, double log_prior, double* logp,
+                                bioem_best* best);
+
 // Ensemble posterior over models (weights w [nm], device): per [ni] and
 // total [1] from logp [nm][ni]; per may only be null when ni == 0.
 hipError_t launch_ensemble(hipStream_t s, const double* logp, int nm, int ni, const double* w, double* per,
