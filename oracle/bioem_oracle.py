@@ -341,7 +341,9 @@ def logpost_oracle(images: np.ndarray, spheres: np.ndarray, quats: np.ndarray,
                 for i in range(ni):
                     for dy in range(2 * S + 1):
                         for dx in range(2 * S + 1):
-                            per_c[i, c, dy, dx] = log_likelihood(X[i, dy, dx], A[i], Bd[dy, dx], n)
+                            # nothing moved in (B = 0): that displacement is left out
+                            per_c[i, c, dy, dx] = (log_likelihood(X[i, dy, dx], A[i], Bd[dy, dx], n)
+                                                   if Bd[dy, dx] > 0.0 else -np.inf)
                 continue
             B = projection_norm(i1)
             X = corr(imgs, i1, S)
