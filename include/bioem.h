@@ -328,7 +328,8 @@ bioem_status bioem_get_kernel_time(bioem_ctx* ctx, double* ms, int32_t* launches
  * EINVAL: bad pointers, sizes or memory kinds, max_shift < 0 or
  * 2*max_shift >= min(nx, ny), non-finite CTF values or A outside [0, 1].
  * EUNSUPPORTED: max_shift > 3, or a box too wide for the kernel's LDS
- * staging at that window (16 x (2S+1) rows of nx + 2S floats). */
+ * staging at that window (32 rows of nx + 1 floats and 8 x (2S+1) rows of
+ * nx + 2S floats within 160 KB). */
 bioem_status bioem_logpost_crop(bioem_ctx* ctx, const bioem_proj* proj, const float* imgs, int32_t ni,
                                 int32_t in_mem, const double* ctf, int32_t nc, int32_t max_shift, double* logp,
                                 bioem_best* best, int32_t out_mem);

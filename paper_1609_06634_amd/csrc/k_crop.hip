@@ -14,11 +14,12 @@
 // correlation: W = (2S+1)^2 multiply-adds per pixel and evaluation, so it
 // only pays for small windows.
 //
-// k_crop_xcorr: a workgroup takes 16 images x 16 calculated images; row by
-// row it stages the images' centred rows and the calculated images' 2S+1
-// rows around it (zero outside the box, S zero columns on each side) in
-// LDS, and each thread forms one pair's W correlations of that row in FP32,
-// added to FP64 accumulators once per row.  Then the FP64 likelihood per d,
+// k_crop_xcorr: a workgroup takes 32 images x 8 calculated images; row by
+// row it stages the images' centred rows in LDS and keeps the calculated
+// images' 2S+1 rows around it in an LDS ring (one new row per step; zero
+// outside the box, S zero columns on each side), and each thread forms one
+// pair's W correlations of that row in FP32 from a register window, added
+// to FP64 accumulators once per row.  Then the FP64 likelihood per d,
 // and one record per evaluation: the window maximum l_max, the relative sum
 // sum_d exp(l(d) - l_max) and the argmax (lowest (dy, dx) on ties).
 #include "common.hpp"
@@ -27,8 +28,9 @@ namespace bioem {
 
 namespace {
 
-constexpr int kTile = 16;          // images and calculated images per workgroup
-constexpr int kXThreads = kTile * kTile;
+constexpr int kTileI = 32;         // images per workgroup
+constexpr int kTileP = 8;          // calculated images per workgroup
+constexpr int kXThreads = kTileI * kTileP;
 constexpr int kSumThreads = 256;
 
 BIOEM_DEV double block_sum(double v, double* red) {
@@ -72,46 +74,73 @@ __global__ __launch_bounds__(kXThreads) void k_crop_xcorr(CropArgs a) {
   constexpr int W1 = 2 * S + 1, W = W1 * W1;
   extern __shared__ float lds[];
   const int nx = a.nx, ny = a.ny, pw = nx + 2 * S, iw = nx + 1;
-  float* Li = lds;                           // [kTile][nx + 1]: centred image rows
-  float* Lp = lds + kTile * iw;              // [kTile][W1][nx + 2S]: calculated rows
-  const int t = threadIdx.x, tq = t % kTile, ti = t / kTile;
-  const int i0 = blockIdx.y * kTile, p0 = blockIdx.x * kTile;
+  float* Li = lds;                           // [kTileI][nx + 1]: centred image rows
+  float* Lp = lds + kTileI * iw;             // [kTileP][W1][nx + 2S]: ring of calculated rows
+  const int t = threadIdx.x, tq = t % kTileP, ti = t / kTileP;
+  const int i0 = blockIdx.y * kTileI, p0 = blockIdx.x * kTileP;
   const double n = (double)nx * ny;
-  for (int e = t; e < kTile * W1; e += kXThreads)
+  // calculated row kk (-S <= kk < ny + S) lives in ring slot (kk + S) mod W1;
+  // columns 0..S-1 and S+nx.. of every slot stay zero
+  auto load_prow = [&](int kk) {
+    const int slot = (kk + S) % W1;
+    for (int e = t; e < kTileP * nx; e += kXThreads) {
+      const int b = e / nx, j = e % nx, pi = p0 + b;
+      float v = 0.0f;
+      if (pi < a.np && kk >= 0 && kk < ny) v = a.p[((size_t)pi * ny + kk) * nx + j];
+      Lp[(b * W1 + slot) * pw + S + j] = v;
+    }
+  };
+  for (int e = t; e < kTileP * W1; e += kXThreads)
     for (int c = 0; c < S; ++c) {
       Lp[e * pw + c] = 0.0f;
       Lp[e * pw + S + nx + c] = 0.0f;
     }
+  for (int kk = -S; kk < S; ++kk) load_prow(kk);
   double acc[W];
 #pragma unroll
   for (int w = 0; w < W; ++w) acc[w] = 0.0;
   for (int k = 0; k < ny; ++k) {
-    __syncthreads();   // the previous row's reads are done (and the pads are set)
-    for (int e = t; e < kTile * nx; e += kXThreads) {
+    __syncthreads();   // the previous row's reads are done (and the pads and first rows are set)
+    for (int e = t; e < kTileI * nx; e += kXThreads) {
       const int b = e / nx, j = e % nx, i = i0 + b;
       float v = 0.0f;
       if (i < a.ni) v = (float)((double)a.imgs[((size_t)i * ny + k) * nx + j] - a.stats[3 * i] / n);
       Li[b * iw + j] = v;
     }
-    for (int e = t; e < kTile * W1 * nx; e += kXThreads) {
-      const int b = e / (W1 * nx), rem = e % (W1 * nx), r = rem / nx, j = rem % nx;
-      const int kk = k + r - S, pi = p0 + b;
-      float v = 0.0f;
-      if (pi < a.np && kk >= 0 && kk < ny) v = a.p[((size_t)pi * ny + kk) * nx + j];
-      Lp[(b * W1 + r) * pw + S + j] = v;
-    }
+    load_prow(k + S);
     __syncthreads();
     float row[W];
 #pragma unroll
     for (int w = 0; w < W; ++w) row[w] = 0.0f;
     const float* li = Li + ti * iw;
-    for (int j = 0; j < nx; ++j) {
-      const float ic = li[j];
+    // rows k - S .. k + S of this thread's calculated image
+    const float* lp[W1];
 #pragma unroll
-      for (int dy = 0; dy < W1; ++dy) {
-        const float* lp = Lp + (tq * W1 + dy) * pw + j;
+    for (int dy = 0; dy < W1; ++dy) lp[dy] = Lp + (tq * W1 + (k + dy) % W1) * pw;
+    // win[dy][slot]: a sliding window of 2S+1 columns per calculated row in
+    // registers; at column j, column j + dx sits in slot (j + dx) mod W1, so
+    // with j unrolled by W1 every slot index is a constant and the window
+    // advances by one LDS read per row instead of W1
+    float win[W1][W1];
 #pragma unroll
-        for (int dx = 0; dx < W1; ++dx) row[dy * W1 + dx] = fmaf(ic, lp[dx], row[dy * W1 + dx]);
+    for (int dy = 0; dy < W1; ++dy)
+#pragma unroll
+      for (int dx = 0; dx < W1; ++dx) win[dy][dx] = lp[dy][dx];
+    for (int jb = 0; jb < nx; jb += W1) {
+#pragma unroll
+      for (int u = 0; u < W1; ++u) {
+        const int j = jb + u;
+        if (j < nx) {
+          const float ic = li[j];
+          const int nxt = min(j + W1, pw - 1);   // column j + 2S + 1 (unused past the row's end)
+#pragma unroll
+          for (int dy = 0; dy < W1; ++dy) {
+#pragma unroll
+            for (int dx = 0; dx < W1; ++dx)
+              row[dy * W1 + dx] = fmaf(ic, win[dy][(u + dx) % W1], row[dy * W1 + dx]);
+            win[dy][u] = lp[dy][nxt];
+          }
+        }
       }
     }
 #pragma unroll
@@ -231,7 +260,7 @@ __global__ __launch_bounds__(kSumThreads) void k_crop_finalize(CropArgs a, doubl
 }  // namespace
 
 size_t crop_smem_bytes(int nx, int S) {
-  return sizeof(float) * ((size_t)kTile * (nx + 1) + (size_t)kTile * (2 * S + 1) * (nx + 2 * S));
+  return sizeof(float) * ((size_t)kTileI * (nx + 1) + (size_t)kTileP * (2 * S + 1) * (nx + 2 * S));
 }
 
 hipError_t launch_crop_norms(hipStream_t s, const CropArgs& a) {
@@ -240,7 +269,7 @@ hipError_t launch_crop_norms(hipStream_t s, const CropArgs& a) {
 }
 
 hipError_t launch_crop_xcorr(hipStream_t s, const CropArgs& a) {
-  const dim3 grid((a.np + kTile - 1) / kTile, (a.ni + kTile - 1) / kTile);
+  const dim3 grid((a.np + kTileP - 1) / kTileP, (a.ni + kTileI - 1) / kTileI);
   const size_t smem = crop_smem_bytes(a.nx, a.S);
   if (smem > kMaxSmem) return hipErrorInvalidValue;
   const void* fn = nullptr;
