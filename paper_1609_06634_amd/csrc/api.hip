@@ -730,6 +730,7 @@ bioem_status bioem_logpost_crop(bioem_ctx* ctx, const bioem_proj* proj, const fl
   if (!proj || !imgs || !ctf || !logp || !best || ni < 1 || nc < 1 || !valid_mem(in_mem) || !valid_mem(out_mem))
     return fail(ctx, BIOEM_EINVAL, "bioem_logpost_crop: bad argument");
   const int nx = proj->nx, ny = proj->ny, nq = proj->n, S = max_shift;
+  if (proj->device != ctx->device) return fail(ctx, BIOEM_EINVAL, "bioem_logpost_crop: handle on another device");
   if (S < 0 || 2 * S >= std::min(nx, ny))
     return fail(ctx, BIOEM_EINVAL, "bioem_logpost_crop: max_shift %d outside [0, min(nx, ny)/2)", S);
   if (S > kCropMaxShift || crop_smem_bytes(nx, S) > kMaxSmem)
