@@ -47,6 +47,24 @@ def quat_to_matrix(q: Sequence[float]) -> np.ndarray:
     ])
 
 
+def euler_to_matrix(phi: float, theta: float, psi: float) -> np.ndarray:
+    """Rotation matrix of Euler angles (radians), the other orientation
+    representation of Section 3 (Model rotation): rotate about z by phi,
+    then about the new y by theta, then about the new z by psi (intrinsic
+    z-y-z), i.e. R = Rz(phi) Ry(theta) Rz(psi) acting on column vectors.
+    The paper does not fix the convention; z-y-z is the usual one in EM.
+    """
+    def rz(a):
+        c, s = math.cos(a), math.sin(a)
+        return np.array([[c, -s, 0.0], [s, c, 0.0], [0.0, 0.0, 1.0]])
+
+    def ry(a):
+        c, s = math.cos(a), math.sin(a)
+        return np.array([[c, 0.0, s], [0.0, 1.0, 0.0], [-s, 0.0, c]])
+
+    return rz(phi) @ ry(theta) @ rz(psi)
+
+
 def _pixel_integrals(centres: np.ndarray, pos: np.ndarray, sigma: np.ndarray,
                      pixel: float) -> np.ndarray:
     """[n_spheres][n_pixels] integral of a unit 1-D Gaussian over each pixel."""

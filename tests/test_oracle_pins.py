@@ -313,3 +313,23 @@ def test_p9_envelope_is_gaussian_blur():
     r = O.signed_freq(n)
     g = np.exp(-(r[:, None] ** 2 + r[None, :] ** 2) / (2 * sig2)) / (2 * math.pi * sig2)
     np.testing.assert_allclose(psf, -g, atol=1e-9)
+
+
+# ---------------------------------------------------------------------------
+# Euler angles (the second orientation representation): convention pinned to
+# a library rotation and to its special cases
+# ---------------------------------------------------------------------------
+
+def test_euler_zyz_matches_library_and_special_cases():
+    from scipy.spatial.transform import Rotation
+    rng = np.random.default_rng(51)
+    for phi, theta, psi in rng.uniform(-math.pi, math.pi, (20, 3)):
+        R = O.euler_to_matrix(phi, theta, psi)
+        np.testing.assert_allclose(R, Rotation.from_euler("ZYZ", [phi, theta, psi]).as_matrix(), atol=1e-14)
+        np.testing.assert_allclose(R @ R.T, np.eye(3), atol=1e-14)
+        assert abs(np.linalg.det(R) - 1.0) < 1e-14
+        # no tilt: one rotation about z by phi + psi
+        np.testing.assert_allclose(O.euler_to_matrix(phi, 0.0, psi), O.euler_to_matrix(phi + psi, 0.0, 0.0),
+                                   atol=1e-14)
+    # a quarter turn about y maps z to x
+    np.testing.assert_allclose(O.euler_to_matrix(0.0, math.pi / 2, 0.0) @ [0, 0, 1], [1, 0, 0], atol=1e-15)
