@@ -309,6 +309,16 @@ bioem_status bioem_render(bioem_ctx* ctx, const bioem_proj* proj, const double* 
 bioem_status bioem_set_timing(bioem_ctx* ctx, int32_t enable);
 bioem_status bioem_get_kernel_time(bioem_ctx* ctx, double* ms, int32_t* launches, double* evals);
 
+/* Projections for orientations given as Euler angles, the other
+ * representation of Section 3 (Model rotation): euler [nq][3] (phi, theta,
+ * psi) in radians, z-y-z intrinsic, i.e. the rotation Rz(phi) Ry(theta)
+ * Rz(psi) of the model about its origin.  The angles are turned into unit
+ * quaternions on the device and projected exactly as bioem_project does;
+ * arguments, ownership and errors as there (EINVAL also for a non-finite
+ * angle).  A symmetry-restricted search passes the restricted angle set. */
+bioem_status bioem_project_euler(bioem_ctx* ctx, const double* spheres, int32_t ns, const double* euler, int32_t nq,
+                                 int32_t nx, int32_t ny, double pixel_A, bioem_mem in_mem, bioem_proj** out);
+
 /* Real-space variant of the displacement sum (Section 3, Center
  * displacement) with border cropping instead of the Fourier variant's wrap:
  * the calculated image moved by d keeps I1(r + d) where r + d lies in the

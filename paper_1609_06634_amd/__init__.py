@@ -4,7 +4,7 @@ The computation lives in libbioem.so (include/bioem.h); this package only
 builds it and marshals arguments to it.
 """
 from .bindings import (  # noqa: F401
-    Context, Projections, Images, BioemError, project, prepare_images, logpost, render,
+    Context, Projections, Images, BioemError, project, project_euler, prepare_images, logpost, render,
     ctf_from_physical, version, load, best_from_bytes, BEST_DTYPE, LIB_PATH, logpost_batch, Net, topk, cnn_input, ensemble, logpost_crop,
 )
 

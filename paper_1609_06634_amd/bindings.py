@@ -82,6 +82,7 @@ SIGNATURES = [
     ("bioem_last_error", ctypes.c_char_p, [_P]),
     ("bioem_version", ctypes.c_char_p, []),
     ("bioem_project", _I, [_P, _P, _I, _P, _I, _I, _I, _D, _I, ctypes.POINTER(_P)]),
+    ("bioem_project_euler", _I, [_P, _P, _I, _P, _I, _I, _I, _D, _I, ctypes.POINTER(_P)]),
     ("bioem_prepare_images", _I, [_P, _P, _I, _I, _I, _I, ctypes.POINTER(_P)]),
     ("bioem_logpost", _I, [_P, _P, _P, _P, _I, _I, _I, ctypes.POINTER(Opts), _P, _P]),
     ("bioem_render", _I, [_P, _P, _P, _P, _P, _P, _D, _I, _P, _I]),
@@ -254,6 +255,20 @@ def project(ctx: Context, spheres, quats, nx: int, ny: int, pixel_A: float) -> P
     nq = (k2.shape[0] if hasattr(k2, "shape") else len(k2))
     h = ctypes.c_void_p()
     ctx.check(ctx._lib.bioem_project(ctx.h, sp, ns, qp, nq, nx, ny, pixel_A, m1, ctypes.byref(h)))
+    return Projections(ctx._lib, h)
+
+
+def project_euler(ctx: Context, spheres, euler, nx: int, ny: int, pixel_A: float) -> Projections:
+    """Projections for z-y-z Euler angles [nq][3] (radians) instead of quaternions."""
+    sp, m1, k1 = _arg(spheres, np.float64)
+    ep, m2, k2 = _arg(euler, np.float64)
+    if m1 != m2:
+        raise ValueError("spheres and euler must both be host or both device")
+    if len(k2.shape) != 2 or k2.shape[1] != 3:
+        raise ValueError("euler must be [nq][3]")
+    h = ctypes.c_void_p()
+    ctx.check(ctx._lib.bioem_project_euler(ctx.h, sp, int(k1.shape[0]), ep, int(k2.shape[0]), nx, ny, pixel_A, m1,
+                                           ctypes.byref(h)))
     return Projections(ctx._lib, h)
 
 

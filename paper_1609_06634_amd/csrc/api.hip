@@ -723,6 +723,27 @@ bioem_status bioem_tuning_entry(const bioem_ctx* ctx, int32_t idx, bioem_tuning*
   return BIOEM_OK;
 }
 
+bioem_status bioem_project_euler(bioem_ctx* ctx, const double* spheres, int32_t ns, const double* euler, int32_t nq,
+                                 int32_t nx, int32_t ny, double pixel_A, bioem_mem in_mem, bioem_proj** out) {
+  if (!ctx) return BIOEM_EINVAL;
+  if (!out) return fail(ctx, BIOEM_EINVAL, "bioem_project_euler: out is NULL");
+  *out = nullptr;
+  if (!spheres || !euler || ns < 1 || nq < 1 || !valid_mem(in_mem))
+    return fail(ctx, BIOEM_EINVAL, "bioem_project_euler: bad argument");
+  HIP_OR_FAIL(ctx, hipSetDevice(ctx->device));
+  hipStream_t s = ctx->stream;
+  std::vector<double> he;
+  HIP_OR_FAIL(ctx, to_host(euler, (size_t)nq * 3, in_mem, s, he));
+  if (!finite_all(he.data(), he.size())) return fail(ctx, BIOEM_EINVAL, "bioem_project_euler: non-finite angle");
+  DevIn de, dsp;
+  HIP_OR_FAIL(ctx, de.set(euler, sizeof(double) * 3 * (size_t)nq, in_mem, s));
+  HIP_OR_FAIL(ctx, dsp.set(spheres, sizeof(double) * 5 * (size_t)ns, in_mem, s));
+  DevMem dq;
+  HIP_OR_FAIL(ctx, dq.alloc(sizeof(double) * 4 * (size_t)nq));
+  HIP_OR_FAIL(ctx, launch_euler_quat(s, de.as<double>(), nq, dq.as<double>()));
+  return bioem_project(ctx, dsp.as<double>(), ns, dq.as<double>(), nq, nx, ny, pixel_A, BIOEM_MEM_DEVICE, out);
+}
+
 bioem_status bioem_logpost_crop(bioem_ctx* ctx, const bioem_proj* proj, const float* imgs, int32_t ni,
                                 int32_t in_mem, const double* ctf, int32_t nc, int32_t max_shift, double* logp,
                                 bioem_best* best, int32_t out_mem) {

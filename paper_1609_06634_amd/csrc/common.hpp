@@ -82,6 +82,8 @@ hipError_t launch_rdft2(hipStream_t s, const double* real_in, const float* real_
 hipError_t launch_spec_store(hipStream_t s, const double2* spec64, int n, int nx, int ny,
                              float2* spec, int32_t* expo);
 hipError_t launch_image_stats(hipStream_t s, const float* imgs, int n, int npix, double* stats);
+// z-y-z Euler angles [n][3] (radians) -> unit quaternions [n][4] (w, x, y, z).
+hipError_t launch_euler_quat(hipStream_t s, const double* euler, int n, double* quats);
 // Fragment-order copies: complex spectra [n][nx/2+1][spec_ld(ny)] -> [n][tile_spec_len],
 // real tables [n][nx/2+1][spec_ld(ny)] -> [n][tile_table_len] (rows l = 32 ks + 8 g + 4 r .. +3, r < 2).
 hipError_t launch_tile_spec(hipStream_t s, const float2* spec, int n, int nx, int ny, float4* tile);

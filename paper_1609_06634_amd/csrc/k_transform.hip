@@ -532,6 +532,34 @@ hipError_t launch_image_stats(hipStream_t s, const float* imgs, int n, int npix,
   return last();
 }
 
+// Unit quaternion (w, x, y, z) of z-y-z Euler angles (phi, theta, psi):
+// q = qz(phi) qy(theta) qz(psi) (Hamilton products), the rotation
+// Rz(phi) Ry(theta) Rz(psi).
+BIOEM_DEV double4 qmul(double4 a, double4 b) {
+  return make_double4(a.x * b.x - a.y * b.y - a.z * b.z - a.w * b.w, a.x * b.y + a.y * b.x + a.z * b.w - a.w * b.z,
+                      a.x * b.z - a.y * b.w + a.z * b.x + a.w * b.y, a.x * b.w + a.y * b.z - a.z * b.y + a.w * b.x);
+}
+
+__global__ __launch_bounds__(256) void k_euler_quat(const double* __restrict__ e, int n, double* __restrict__ q) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= n) return;
+  double s1, c1, s2, c2, s3, c3;
+  sincos(0.5 * e[3 * i], &s1, &c1);
+  sincos(0.5 * e[3 * i + 1], &s2, &c2);
+  sincos(0.5 * e[3 * i + 2], &s3, &c3);
+  const double4 r = qmul(qmul(make_double4(c1, 0.0, 0.0, s1), make_double4(c2, 0.0, s2, 0.0)),
+                         make_double4(c3, 0.0, 0.0, s3));
+  q[4 * i] = r.x;
+  q[4 * i + 1] = r.y;
+  q[4 * i + 2] = r.z;
+  q[4 * i + 3] = r.w;
+}
+
+hipError_t launch_euler_quat(hipStream_t s, const double* euler, int n, double* quats) {
+  hipLaunchKernelGGL(k_euler_quat, dim3((n + 255) / 256), dim3(256), 0, s, euler, n, quats);
+  return last();
+}
+
 hipError_t launch_render(hipStream_t s, const float2* spec, const int32_t* expo, int n, int nx,
                          int ny, double pixel, const double* ctf, const int32_t* shifts,
                          const double* norm_offset, const float* noise, double snr,
