@@ -14,7 +14,9 @@ Every function is pinned by CPU tests against facts fixed by the paper or by
 mathematics (brute-force integration of the likelihood, exact invariances,
 Plancherel, direct-vs-FFT correlation, shift equivariance, parameter
 recovery, high-precision log-sum-exp, projection mass and symmetry, CTF
-special values).  The absolute level of log P depends on the prior reading
+special values; for the ensemble posterior, the cropping real-space variant
+and Euler angles: 50-digit sums, zero-padded FFT correlation, a library
+rotation).  The absolute level of log P depends on the prior reading
 (flat N and mu, Jeffreys lambda, uniform normalised grid priors); the paper
 prints no posterior values, so that level is "parity unpinned" beyond the
 closed-form integral itself.
