@@ -41,8 +41,8 @@ template <> struct Prec<true> {
     const uint32_t b0 = __float_as_uint(x0) & 0xffff0000u, b1 = __float_as_uint(x1) & 0xffff0000u;
     hi = (b0 >> 16) | b1;
     const float l0 = x0 - __uint_as_float(b0), l1 = x1 - __uint_as_float(b1);
-    const __bf16 c0 = (__bf16)l0, c1 = (__bf16)l1;
-    lo = (uint32_t)__builtin_bit_cast(uint16_t, c0) | ((uint32_t)__builtin_bit_cast(uint16_t, c1) << 16);
+    // both remainders rounded (RNE) and packed by one instruction
+    asm("v_cvt_pk_bf16_f32 %0, %1, %2" : "=v"(lo) : "v"(l0), "v"(l1));
   }
 };
 
