@@ -338,8 +338,8 @@ bioem_status bioem_project_euler(bioem_ctx* ctx, const double* spheres, int32_t 
  * EINVAL: bad pointers, sizes or memory kinds, max_shift < 0 or
  * 2*max_shift >= min(nx, ny), non-finite CTF values or A outside [0, 1].
  * EUNSUPPORTED: max_shift > 3, or a box too wide for the kernel's LDS
- * staging at that window (32 rows of nx + 1 floats and 8 x (2S+1) rows of
- * nx + 2S floats within 160 KB). */
+ * staging at that window (32 rows of nx + 1 floats and p x (2S+1) rows of
+ * nx + 2S floats within 160 KB, p = 32, 16, 8, 8 for S = 0, 1, 2, 3). */
 bioem_status bioem_logpost_crop(bioem_ctx* ctx, const bioem_proj* proj, const float* imgs, int32_t ni,
                                 int32_t in_mem, const double* ctf, int32_t nc, int32_t max_shift, double* logp,
                                 bioem_best* best, int32_t out_mem);

@@ -14,7 +14,8 @@
 // correlation: W = (2S+1)^2 multiply-adds per pixel and evaluation, so it
 // only pays for small windows.
 //
-// k_crop_xcorr: a workgroup takes 32 images x 8 calculated images; row by
+// k_crop_xcorr: a workgroup takes 32 images x 8 calculated images (32 with
+// S = 0, 16 with S = 1, four or two per thread); row by
 // row it stages the images' centred rows in LDS and keeps the calculated
 // images' 2S+1 rows around it in an LDS ring (one new row per step; zero
 // outside the box, S zero columns on each side), and each thread forms one
@@ -29,8 +30,12 @@ namespace bioem {
 namespace {
 
 constexpr int kTileI = 32;         // images per workgroup
-constexpr int kTileP = 8;          // calculated images per workgroup
+constexpr int kTileP = 8;          // threads along calculated images per workgroup
 constexpr int kXThreads = kTileI * kTileP;
+// Calculated images per thread: small windows have few accumulators, so each
+// thread takes several calculated images and every staged image row serves
+// more of them.
+__host__ __device__ constexpr int crop_ppt(int S) { return S == 0 ? 4 : (S == 1 ? 2 : 1); }
 constexpr int kSumThreads = 256;
 
 BIOEM_DEV double block_sum(double v, double* red) {
@@ -71,34 +76,37 @@ __global__ __launch_bounds__(kSumThreads) void k_crop_norms(const float* __restr
 
 template <int S>
 __global__ __launch_bounds__(kXThreads) void k_crop_xcorr(CropArgs a) {
-  constexpr int W1 = 2 * S + 1, W = W1 * W1;
+  constexpr int W1 = 2 * S + 1, W = W1 * W1, PPT = crop_ppt(S), TP = kTileP * PPT;
   extern __shared__ float lds[];
   const int nx = a.nx, ny = a.ny, pw = nx + 2 * S, iw = nx + 1;
   float* Li = lds;                           // [kTileI][nx + 1]: centred image rows
-  float* Lp = lds + kTileI * iw;             // [kTileP][W1][nx + 2S]: ring of calculated rows
+  float* Lp = lds + kTileI * iw;             // [TP][W1][nx + 2S]: ring of calculated rows
+  // thread (ti, tq) takes image i0 + ti and calculated images p0 + tq + kTileP m, m < PPT
   const int t = threadIdx.x, tq = t % kTileP, ti = t / kTileP;
-  const int i0 = blockIdx.y * kTileI, p0 = blockIdx.x * kTileP;
+  const int i0 = blockIdx.y * kTileI, p0 = blockIdx.x * TP;
   const double n = (double)nx * ny;
   // calculated row kk (-S <= kk < ny + S) lives in ring slot (kk + S) mod W1;
   // columns 0..S-1 and S+nx.. of every slot stay zero
   auto load_prow = [&](int kk) {
     const int slot = (kk + S) % W1;
-    for (int e = t; e < kTileP * nx; e += kXThreads) {
+    for (int e = t; e < TP * nx; e += kXThreads) {
       const int b = e / nx, j = e % nx, pi = p0 + b;
       float v = 0.0f;
       if (pi < a.np && kk >= 0 && kk < ny) v = a.p[((size_t)pi * ny + kk) * nx + j];
       Lp[(b * W1 + slot) * pw + S + j] = v;
     }
   };
-  for (int e = t; e < kTileP * W1; e += kXThreads)
+  for (int e = t; e < TP * W1; e += kXThreads)
     for (int c = 0; c < S; ++c) {
       Lp[e * pw + c] = 0.0f;
       Lp[e * pw + S + nx + c] = 0.0f;
     }
   for (int kk = -S; kk < S; ++kk) load_prow(kk);
-  double acc[W];
+  double acc[PPT][W];
 #pragma unroll
-  for (int w = 0; w < W; ++w) acc[w] = 0.0;
+  for (int m = 0; m < PPT; ++m)
+#pragma unroll
+    for (int w = 0; w < W; ++w) acc[m][w] = 0.0;
   for (int k = 0; k < ny; ++k) {
     __syncthreads();   // the previous row's reads are done (and the pads and first rows are set)
     for (int e = t; e < kTileI * nx; e += kXThreads) {
@@ -109,23 +117,29 @@ __global__ __launch_bounds__(kXThreads) void k_crop_xcorr(CropArgs a) {
     }
     load_prow(k + S);
     __syncthreads();
-    float row[W];
+    float row[PPT][W];
 #pragma unroll
-    for (int w = 0; w < W; ++w) row[w] = 0.0f;
+    for (int m = 0; m < PPT; ++m)
+#pragma unroll
+      for (int w = 0; w < W; ++w) row[m][w] = 0.0f;
     const float* li = Li + ti * iw;
-    // rows k - S .. k + S of this thread's calculated image
-    const float* lp[W1];
+    // rows k - S .. k + S of this thread's calculated images
+    const float* lp[PPT][W1];
 #pragma unroll
-    for (int dy = 0; dy < W1; ++dy) lp[dy] = Lp + (tq * W1 + (k + dy) % W1) * pw;
-    // win[dy][slot]: a sliding window of 2S+1 columns per calculated row in
-    // registers; at column j, column j + dx sits in slot (j + dx) mod W1, so
-    // with j unrolled by W1 every slot index is a constant and the window
+    for (int m = 0; m < PPT; ++m)
+#pragma unroll
+      for (int dy = 0; dy < W1; ++dy) lp[m][dy] = Lp + ((tq + kTileP * m) * W1 + (k + dy) % W1) * pw;
+    // win[m][dy][slot]: a sliding window of 2S+1 columns per calculated row
+    // in registers; at column j, column j + dx sits in slot (j + dx) mod W1,
+    // so with j unrolled by W1 every slot index is a constant and the window
     // advances by one LDS read per row instead of W1
-    float win[W1][W1];
+    float win[PPT][W1][W1];
 #pragma unroll
-    for (int dy = 0; dy < W1; ++dy)
+    for (int m = 0; m < PPT; ++m)
 #pragma unroll
-      for (int dx = 0; dx < W1; ++dx) win[dy][dx] = lp[dy][dx];
+      for (int dy = 0; dy < W1; ++dy)
+#pragma unroll
+        for (int dx = 0; dx < W1; ++dx) win[m][dy][dx] = lp[m][dy][dx];
     for (int jb = 0; jb < nx; jb += W1) {
 #pragma unroll
       for (int u = 0; u < W1; ++u) {
@@ -134,48 +148,57 @@ __global__ __launch_bounds__(kXThreads) void k_crop_xcorr(CropArgs a) {
           const float ic = li[j];
           const int nxt = min(j + W1, pw - 1);   // column j + 2S + 1 (unused past the row's end)
 #pragma unroll
-          for (int dy = 0; dy < W1; ++dy) {
+          for (int m = 0; m < PPT; ++m)
 #pragma unroll
-            for (int dx = 0; dx < W1; ++dx)
-              row[dy * W1 + dx] = fmaf(ic, win[dy][(u + dx) % W1], row[dy * W1 + dx]);
-            win[dy][u] = lp[dy][nxt];
-          }
+            for (int dy = 0; dy < W1; ++dy) {
+#pragma unroll
+              for (int dx = 0; dx < W1; ++dx)
+                row[m][dy * W1 + dx] = fmaf(ic, win[m][dy][(u + dx) % W1], row[m][dy * W1 + dx]);
+              win[m][dy][u] = lp[m][dy][nxt];
+            }
         }
       }
     }
 #pragma unroll
-    for (int w = 0; w < W; ++w) acc[w] += (double)row[w];
+    for (int m = 0; m < PPT; ++m)
+#pragma unroll
+      for (int w = 0; w < W; ++w) acc[m][w] += (double)row[m][w];
   }
-  const int i = i0 + ti, pi = p0 + tq;
-  if (i >= a.ni || pi >= a.np) return;
+  const int i = i0 + ti;
+  if (i >= a.ni) return;
   const double A = a.stats[3 * i + 2], h = 0.5 * n;
-  bioem_crec rec{-INFINITY, 0.0, -1, 0};
-  if (A > 0.0) {
-    const double kn = lgamma(h - 1.0) - log(2.0) - 0.5 * log(n) + (1.0 - h) * log(M_PI * A);
-    const double* B = a.Bd + (size_t)pi * W;
-    auto ll = [&](int w) -> double {
-      if (!(B[w] > 0.0)) return -INFINITY;
-      const double rho2 = fmin(acc[w] * acc[w] / (A * B[w]), 1.0 - 0x1p-52);
-      return kn - 0.5 * log(B[w]) + (1.0 - h) * log1p(-rho2);
-    };
-    double lmax = -INFINITY;
-    int dmax = -1;
+  const double kn = A > 0.0 ? lgamma(h - 1.0) - log(2.0) - 0.5 * log(n) + (1.0 - h) * log(M_PI * A) : 0.0;
 #pragma unroll
-    for (int w = 0; w < W; ++w) {
-      const double v = ll(w);
-      if (v > lmax) {
-        lmax = v;
-        dmax = w;
+  for (int m = 0; m < PPT; ++m) {
+    const int pi = p0 + tq + kTileP * m;
+    if (pi >= a.np) continue;
+    bioem_crec rec{-INFINITY, 0.0, -1, 0};
+    if (A > 0.0) {
+      const double* B = a.Bd + (size_t)pi * W;
+      auto ll = [&](int w) -> double {
+        if (!(B[w] > 0.0)) return -INFINITY;
+        const double rho2 = fmin(acc[m][w] * acc[m][w] / (A * B[w]), 1.0 - 0x1p-52);
+        return kn - 0.5 * log(B[w]) + (1.0 - h) * log1p(-rho2);
+      };
+      double lmax = -INFINITY;
+      int dmax = -1;
+#pragma unroll
+      for (int w = 0; w < W; ++w) {
+        const double v = ll(w);
+        if (v > lmax) {
+          lmax = v;
+          dmax = w;
+        }
       }
-    }
-    double s = 0.0;
-    if (dmax >= 0) {
+      double sum = 0.0;
+      if (dmax >= 0) {
 #pragma unroll
-      for (int w = 0; w < W; ++w) s += exp(ll(w) - lmax);
+        for (int w = 0; w < W; ++w) sum += exp(ll(w) - lmax);
+      }
+      rec = bioem_crec{lmax, sum, dmax, 0};
     }
-    rec = bioem_crec{lmax, s, dmax, 0};
+    a.rec[(size_t)i * a.np + pi] = rec;
   }
-  a.rec[(size_t)i * a.np + pi] = rec;
 }
 
 // Per image: log-sum-exp over calculated images of l_max + ln(relative sum),
@@ -260,7 +283,7 @@ __global__ __launch_bounds__(kSumThreads) void k_crop_finalize(CropArgs a, doubl
 }  // namespace
 
 size_t crop_smem_bytes(int nx, int S) {
-  return sizeof(float) * ((size_t)kTileI * (nx + 1) + (size_t)kTileP * (2 * S + 1) * (nx + 2 * S));
+  return sizeof(float) * ((size_t)kTileI * (nx + 1) + (size_t)kTileP * crop_ppt(S) * (2 * S + 1) * (nx + 2 * S));
 }
 
 hipError_t launch_crop_norms(hipStream_t s, const CropArgs& a) {
@@ -269,7 +292,8 @@ hipError_t launch_crop_norms(hipStream_t s, const CropArgs& a) {
 }
 
 hipError_t launch_crop_xcorr(hipStream_t s, const CropArgs& a) {
-  const dim3 grid((a.np + kTileP - 1) / kTileP, (a.ni + kTileI - 1) / kTileI);
+  const int tp = kTileP * crop_ppt(a.S);
+  const dim3 grid((a.np + tp - 1) / tp, (a.ni + kTileI - 1) / kTileI);
   const size_t smem = crop_smem_bytes(a.nx, a.S);
   if (smem > kMaxSmem) return hipErrorInvalidValue;
   const void* fn = nullptr;
