@@ -131,7 +131,8 @@ def main() -> int:
     ap.add_argument("--workload", default="paper224", choices=["paper224", "mixed", "proposal", "crossover"],
                     help="paper224: 224^2, 1000 images x 4608 orientations x 8 CTF sets (default); "
                          "mixed: 96/128/180/224 px classes x two models in one persistent launch; "
-                         "proposal: 128^2 x 36,864 orientations with the learned top-K proposal")
+                         "proposal: 128^2 x 36,864 orientations with the learned top-K proposal; "
+                         "crossover: real-space (cropping) against Fourier forms for S = 0..3 at 224^2")
     ap.add_argument("--train-images", type=int, default=100000)
     ap.add_argument("--epochs", type=int, default=4)
     ap.add_argument("--topk", type=int, default=256)
