@@ -254,6 +254,38 @@ def log_likelihood(X, A: float, B: float, n: int):
     return const + (1.0 - h) * np.log1p(-rho2)
 
 
+def loglik_at(image: np.ndarray, spheres: np.ndarray, q, ctf, pixel: float, dx: int, dy: int,
+              borders: str = "wrap") -> float:
+    """l(q, c, d) of one image at one grid point (Eq. likeli integrated, as
+    ``log_likelihood``), with the correlation at d summed directly:
+    X = sum_r (I_o(r) - mean) I1_d(r), where I1_d(r) = I1((r + d) mod box)
+    for the Fourier variant and I1(r + d) inside the box, 0 outside, with
+    ``borders="crop"`` (then B is taken of I1_d).  -inf where nothing moved
+    in (B = 0)."""
+    img = np.asarray(image, dtype=np.float64)
+    ny, nx = img.shape
+    a, amp, b = ctf
+    i1 = filtered_projection(project_model(spheres, q, nx, ny, pixel),
+                             ctf_envelope_table(a, amp, b, nx, ny, pixel))
+    A = image_moments(img)[2]
+    dx, dy = int(dx), int(dy)
+    if borders == "wrap":
+        moved = np.roll(i1, (-dy, -dx), axis=(0, 1))
+    elif borders == "crop":
+        moved = np.zeros_like(i1)
+        for k in range(ny):
+            for j in range(nx):
+                if 0 <= k + dy < ny and 0 <= j + dx < nx:
+                    moved[k, j] = i1[k + dy, j + dx]
+    else:
+        raise ValueError(f"borders must be 'wrap' or 'crop', not {borders!r}")
+    B = projection_norm(moved)
+    if not B > 0.0:
+        return -math.inf
+    X = math.fsum(((img - img.mean()) * moved).ravel())
+    return float(log_likelihood(X, A, B, nx * ny))
+
+
 def logsumexp_exact(values) -> float:
     """ln sum exp(v) as M + ln fsum(exp(v - M)) in FP64."""
     v = np.asarray(values, dtype=np.float64).ravel()

@@ -86,3 +86,18 @@ def test_cropped_posterior_reduces_to_wrapped_without_shifts():
     d = np.abs(a.logp - b.logp)
     assert d.max() > 0 and np.all(np.isfinite(b.logp))
     assert math.isfinite(float(b.best_logl.max()))
+
+
+def test_loglik_at_crop_reproduces_the_grid_maximum():
+    """The single-point cropped log-likelihood equals the cropped grid
+    evaluation at its maximum (the loop form of the crop against the
+    slicing form of ``correlation_cropped``)."""
+    wl = make_workload(1, n_images=2)
+    cls = wl.classes[0]
+    imgs = O.render_images(cls, wl.models)
+    qs = cls.quats[:4]
+    r = O.logpost_oracle(imgs, wl.models[0], qs, cls.ctf[:2], cls.pixel_A, 3, borders="crop")
+    for i in range(2):
+        l = O.loglik_at(imgs[i], wl.models[0], qs[r.best_q[i]], cls.ctf[r.best_c[i]], cls.pixel_A,
+                        r.best_dx[i], r.best_dy[i], borders="crop")
+        assert abs(l - r.best_logl[i]) <= 1e-10 * abs(l)

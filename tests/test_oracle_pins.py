@@ -219,6 +219,62 @@ def test_p10_posterior_bounds():
         assert abs(O.logsumexp_exact(r.logp_orient[i, qsub]) - r.logp[i]) < 1e-9
 
 
+def _checkerboard_case(S, nq=5, nc=3):
+    """One narrow sphere at the origin (every orientation projects alike),
+    nc identical CTF rows, and a checkerboard image (plus an offset): the
+    centred checkerboard correlates with any calculated image as
+    X(d) = (-1)^(dx+dy) X(0), so l is one value over the whole grid."""
+    nx = ny = 16
+    pixel = 2.0
+    sph = np.array([[0.0, 0.0, 0.0, 0.6, 1.0]])
+    rng = np.random.default_rng(14)
+    quats = rng.standard_normal((nq, 4))
+    quats /= np.linalg.norm(quats, axis=1, keepdims=True)
+    ctf = np.array([[40.0, 0.1, 0.0]] * nc)
+    j, k = np.meshgrid(np.arange(nx), np.arange(ny))
+    cb = np.where((j + k) % 2 == 0, 1.0, -1.0)
+    img = 2.5 + 0.7 * cb
+    i1 = O.filtered_projection(O.project_model(sph, quats[0], nx, ny, pixel),
+                               O.ctf_envelope_table(*ctf[0], nx, ny, pixel))
+    n = nx * ny
+    A = 0.49 * n                                   # sum of (0.7 cb)^2, exactly
+    B = O.projection_norm(i1)
+    X0 = math.fsum((0.7 * cb * i1).ravel())
+    return img, sph, quats, ctf, pixel, O.log_likelihood(X0, A, B, n), X0 * X0 / (A * B)
+
+
+@pytest.mark.parametrize("S", [0, 2, 5])
+def test_p14_prior_normaliser_on_a_constant_likelihood(S):
+    """With l constant over the grid, ln sum exp(l) - ln(Nq Nc Nd) = l exactly
+    whatever the grid sizes: a wrong normaliser (2S+1 shifts instead of
+    (2S+1)^2, or a missing -ln Nq or -ln Nc) is off by its logarithm."""
+    img, sph, quats, ctf, pixel, l0, rho2 = _checkerboard_case(S)
+    assert rho2 > 1e-3                      # a non-trivial correlation term
+    r = O.logpost_oracle(img[None], sph, quats, ctf, pixel, S, method="direct")
+    assert abs(r.logp[0] - l0) <= 1e-10 * abs(l0)
+    assert abs(r.best_logl[0] - l0) <= 1e-10 * abs(l0)
+    nd = (2 * S + 1) ** 2
+    assert abs(r.log_prior + math.log(len(quats) * len(ctf) * nd)) < 1e-12
+    for q in range(len(quats)):             # each orientation holds 1/Nq of the mass
+        assert abs(r.logp_orient[0, q] - (l0 - math.log(len(quats)))) <= 1e-10 * abs(l0)
+
+
+def test_loglik_at_reproduces_the_grid_maximum():
+    """The single-point log-likelihood (used to check reported best points)
+    equals the grid evaluation at its maximum and lies below it elsewhere."""
+    wl = make_workload(1, n_images=2)
+    cls = wl.classes[0]
+    imgs = O.render_images(cls, wl.models)
+    qs = cls.quats[:6]
+    r = O.logpost_oracle(imgs, wl.models[0], qs, cls.ctf, cls.pixel_A, cls.max_shift, method="direct")
+    for i in range(2):
+        l = O.loglik_at(imgs[i], wl.models[0], qs[r.best_q[i]], cls.ctf[r.best_c[i]], cls.pixel_A,
+                        r.best_dx[i], r.best_dy[i])
+        assert abs(l - r.best_logl[i]) <= 1e-10 * abs(l)
+        other = O.loglik_at(imgs[i], wl.models[0], qs[(r.best_q[i] + 1) % 6], cls.ctf[0], cls.pixel_A, 1, -1)
+        assert other <= r.best_logl[i]
+
+
 # ---------------------------------------------------------------------------
 # P8: projection (Eq. ideal)
 # ---------------------------------------------------------------------------
