@@ -70,7 +70,10 @@ typedef enum {
 typedef enum { BIOEM_MEM_HOST = 0, BIOEM_MEM_DEVICE = 1 } bioem_mem;
 
 /* How the inverse transforms of the cross-correlation are computed.
- *   F32:        FP32 direct pruned transform on the vector ALUs.
+ *   F32:        plain FP32: FP32 operands and accumulation throughout, on the
+ *               FP32 matrix cores (factored pruned transform) where the
+ *               shift window allows, else a direct pruned transform on the
+ *               vector ALUs (bioem_opts.kernel selects).
  *   SPLIT_F16:  DFT-as-GEMM on the matrix cores; each FP32 operand is split
  *               into fp16 hi + lo parts, three products, FP32 accumulation
  *               (about 22 significant bits).
@@ -107,7 +110,18 @@ typedef struct {
    * (LSE over CTF sets and shifts, same prior), Section 3 Extra features.
    * Entries not evaluated under a proposal are -inf. */
   double* logp_orient;
-  int32_t reserved[4];     /* must be zero */
+  /* Kernel form, for comparisons and sweeps (0 = the library's choice).
+   *   F32:   1 = FP32 matrix-core form with the factored transform (the
+   *          default where supported: 0 <= S <= 31), 2 = direct pruned
+   *          transform on the vector ALUs (any S);
+   *   split: 1 + launch-shape index (bioem_tuning_count lists the tuned ones).
+   * An unsupported choice returns BIOEM_EUNSUPPORTED. */
+  int32_t kernel;
+  /* Item tile (images x orientation slots walked together for cache reuse)
+   * of the matrix-core kernels; 0 = default (or the autotuned tile). */
+  int32_t tile_images;
+  int32_t tile_slots;
+  int32_t reserved;        /* must be zero */
 } bioem_opts;
 
 /* Create a context on HIP device `device`.  `hip_stream` is the hipStream_t

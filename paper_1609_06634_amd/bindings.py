@@ -44,7 +44,8 @@ BEST_DTYPE = np.dtype({"names": ["logl", "q", "c", "dx", "dy", "status"],
 class Opts(ctypes.Structure):
     _fields_ = [("prec", ctypes.c_int32), ("out_mem", ctypes.c_int32),
                 ("cand_q", ctypes.c_void_p), ("k", ctypes.c_int32), ("cand_mem", ctypes.c_int32),
-                ("logp_orient", ctypes.c_void_p), ("reserved", ctypes.c_int32 * 4)]
+                ("logp_orient", ctypes.c_void_p), ("kernel", ctypes.c_int32),
+                ("tile_images", ctypes.c_int32), ("tile_slots", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class Job(ctypes.Structure):
@@ -281,16 +282,21 @@ def prepare_images(ctx: Context, images) -> Images:
 
 
 def logpost(ctx: Context, proj: Projections, imgs: Images, ctf, max_shift: int,
-            prec: str = "f32", cand_q=None, orient: bool = False, device_out: bool = False):
+            prec: str = "f32", cand_q=None, orient: bool = False, device_out: bool = False,
+            kernel: int = 0, tile=None):
     """Returns dict(logp [ni], best (structured) [ni], orient [ni][nq] or None).
 
     With ``device_out`` the outputs are torch CUDA tensors (best as a raw
-    byte tensor of ni records) and nothing is synchronised."""
+    byte tensor of ni records) and nothing is synchronised.  ``kernel`` and
+    ``tile`` (images, slots) are bioem_opts.kernel / tile_images, tile_slots."""
     cp, cm, ck = _arg(ctf, np.float64)
     nc = int(ck.shape[0])
     ni, nq = imgs.n, proj.n
     o = Opts()
     o.prec = PREC[prec]
+    o.kernel = int(kernel)
+    if tile is not None:
+        o.tile_images, o.tile_slots = int(tile[0]), int(tile[1])
     keep = []
     if cand_q is not None:
         qp, qm, qk = _arg(cand_q, np.int32)

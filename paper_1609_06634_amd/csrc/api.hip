@@ -23,15 +23,6 @@ bool valid_box(int nx, int ny) {
   return nx >= 4 && ny >= 4 && nx <= kMaxBox && ny <= kMaxBox && nx % 2 == 0 && ny % 2 == 0;
 }
 
-// Launch shape of the split kernel: BIOEM_SPLIT_SHAPE overrides the default.
-int split_shape_for(bool bf16) {
-  const char* env = std::getenv("BIOEM_SPLIT_SHAPE");
-  if (env) {
-    const int v = std::atoi(env);
-    if (v >= 0 && v < split_num_shapes()) return v;
-  }
-  return split_shape_for_ew(2, bf16);
-}
 
 // Items per transform chunk so that the FP64 scratch stays within budget.
 int chunk_items(int n, size_t per_item) {
@@ -48,6 +39,7 @@ int chunk_items(int n, size_t per_item) {
 namespace {
 
 constexpr size_t kBatchRecordBudget = size_t(16) << 30;   // records of one persistent launch
+constexpr size_t kProductBudget = size_t(4) << 30;        // image x CTF copies per image chunk (FP32 form)
 
 // A validated bioem_logpost job with its device-side inputs, tables and
 // output staging.
@@ -67,11 +59,15 @@ struct Job {
   bioem_best* best = nullptr;
   double* orient = nullptr;
   size_t len = 0;                  // stored spectrum stride
+  int kernel = 0, ti = 0, ts = 0;  // bioem_opts kernel form and item tile (0 = default)
+  bool mf = false;                 // F32 on the FP32 matrix cores
+  DevMem mftab;                    // its operand tables
   Job() = default;
   Job(Job&&) = default;
 };
 
-bioem_status plan_job(bioem_ctx* ctx, const bioem_job& jb, int prec, int out_mem, Job& J, const char* who) {
+bioem_status plan_job(bioem_ctx* ctx, const bioem_job& jb, int prec, int out_mem, Job& J, const char* who,
+                      int kernel = 0, int ti = 0, int ts = 0) {
   const bioem_proj* proj = jb.proj;
   const bioem_imgs* imgs = jb.imgs;
   if (!proj || !imgs || !jb.ctf) return fail(ctx, BIOEM_EINVAL, "%s: NULL handle or ctf", who);
@@ -99,11 +95,26 @@ bioem_status plan_job(bioem_ctx* ctx, const bioem_job& jb, int prec, int out_mem
     if (!(hc[3 * c + 1] >= 0.0 && hc[3 * c + 1] <= 1.0))
       return fail(ctx, BIOEM_EINVAL, "%s: amplitude contrast of CTF %d outside [0,1]", who, c);
   const bool split = prec != BIOEM_PREC_F32;
-  if (split && !split_supported(nx, ny, S))
-    return fail(ctx, BIOEM_EUNSUPPORTED, "%s: split-precision kernel does not support %dx%d with S=%d", who,
-                nx, ny, S);
-  if (!split && f32_smem_bytes(nx, ny, S) > kMaxSmem)
-    return fail(ctx, BIOEM_EUNSUPPORTED, "%s: shift window too large for the F32 kernel", who);
+  if (ti < 0 || ts < 0 || ti > 4096 || ts > 65536 || (ti > 0) != (ts > 0))
+    return fail(ctx, BIOEM_EINVAL, "%s: item tile %dx%d outside [1, 4096] x [1, 65536]", who, ti, ts);
+  bool mf = false;
+  if (split) {
+    if (kernel < 0 || kernel > split_num_shapes())
+      return fail(ctx, BIOEM_EINVAL, "%s: kernel %d outside [0, %d] for a split precision", who, kernel,
+                  split_num_shapes());
+    if (!split_supported(nx, ny, S))
+      return fail(ctx, BIOEM_EUNSUPPORTED, "%s: split-precision kernel does not support %dx%d with S=%d", who,
+                  nx, ny, S);
+  } else {
+    if (kernel < 0 || kernel > 2) return fail(ctx, BIOEM_EINVAL, "%s: kernel %d outside [0, 2] for F32", who, kernel);
+    mf = kernel != 2 && mf32_supported(nx, ny, S);
+    if (kernel == 1 && !mf)
+      return fail(ctx, BIOEM_EUNSUPPORTED, "%s: FP32 matrix-core kernel does not support %dx%d with S=%d", who, nx,
+                  ny, S);
+  }
+  // the vector-ALU kernel, and the best-displacement pass of the other forms
+  if (f32_smem_bytes(nx, ny, S) > kMaxSmem)
+    return fail(ctx, BIOEM_EUNSUPPORTED, "%s: shift window too large for %dx%d", who, nx, ny);
   std::vector<int32_t> hcand;
   if (jb.cand_q) {
     HIP_OR_FAIL(ctx, to_host(jb.cand_q, (size_t)ni * jb.k, (bioem_mem)jb.cand_mem, s, hcand));
@@ -113,6 +124,7 @@ bioem_status plan_job(bioem_ctx* ctx, const bioem_job& jb, int prec, int out_mem
   }
   J.proj = proj; J.imgs = imgs;
   J.nx = nx; J.ny = ny; J.nq = nq; J.ni = ni; J.nc = nc; J.S = S;
+  J.kernel = kernel; J.ti = ti; J.ts = ts; J.mf = mf;
   J.has_cand = jb.cand_q != nullptr;
   J.k = J.has_cand ? jb.k : 0;
   J.nslots = J.has_cand ? jb.k : nq;
@@ -127,6 +139,10 @@ bioem_status plan_job(bioem_ctx* ctx, const bioem_job& jb, int prec, int out_mem
   if (split) {
     HIP_OR_FAIL(ctx, J.ttable.alloc(sizeof(float4) * tile_table_len(nx, ny) * nc));
     HIP_OR_FAIL(ctx, launch_tile_table(s, J.table.as<float>(), nc, nx, ny, J.ttable.as<float4>()));
+  }
+  if (mf) {
+    HIP_OR_FAIL(ctx, J.mftab.alloc(sizeof(float4) * mf32_table_len(nx, ny)));
+    HIP_OR_FAIL(ctx, launch_mf_tables(s, nx, ny, S, J.mftab.as<float4>()));
   }
   HIP_OR_FAIL(ctx, launch_proj_norms(s, proj->spec, proj->expo, nq, J.table.as<float>(), nc, nx, ny,
                                      J.B.as<double>()));
@@ -242,17 +258,10 @@ bioem_status tune_job(bioem_ctx* ctx, const Job& J, int prec, bioem_tuning& out)
 
 bioem_status split_cfg(bioem_ctx* ctx, const Job& J, int prec, SplitCfg& cfg) {
   const bool bf16 = prec == BIOEM_PREC_SPLIT_BF16;
-  cfg = SplitCfg{split_shape_for(bf16), 2, 0, 0};
-  if (std::getenv("BIOEM_SPLIT_SHAPE") || !ctx->autotune) {
+  cfg = SplitCfg{J.kernel > 0 ? J.kernel - 1 : split_shape_for_ew(2, bf16), 2, J.ti, J.ts};
+  // an explicit launch shape or item tile (bioem_opts) bypasses the autotuner
+  if (J.kernel > 0 || J.ti > 0 || !ctx->autotune) {
     cfg.ew = split_shape_ew(cfg.shape);
-    // BIOEM_SPLIT_TILE=IxS overrides the item tile (images x orientation slots)
-    if (const char* t = std::getenv("BIOEM_SPLIT_TILE")) {
-      int ti = 0, ts = 0;
-      if (std::sscanf(t, "%dx%d", &ti, &ts) == 2 && ti > 0 && ts > 0 && ti <= 4096 && ts <= 65536) {
-        cfg.ti = ti;
-        cfg.ts = ts;
-      }
-    }
     return BIOEM_OK;
   }
   const int lq = ilog2(J.nq);
@@ -280,9 +289,12 @@ bioem_status run_job(bioem_ctx* ctx, Job& J, int prec) {
     if (st != BIOEM_OK) return st;
   }
   const size_t per_image = sizeof(bioem_erec) * (size_t)J.nslots * J.nc;
-  const int chunk = (int)std::max<size_t>(1, std::min<size_t>(J.ni, kRecordBudget / per_image));
-  DevMem rec;
+  int chunk = (int)std::max<size_t>(1, std::min<size_t>(J.ni, kRecordBudget / per_image));
+  const size_t at_image = sizeof(float4) * mf_len(J.nx, J.ny) * J.nc;
+  if (J.mf) chunk = (int)std::max<size_t>(1, std::min<size_t>(chunk, kProductBudget / at_image));
+  DevMem rec, at;
   HIP_OR_FAIL(ctx, rec.alloc(per_image * chunk));
+  if (J.mf) HIP_OR_FAIL(ctx, at.alloc(at_image * chunk));
   const int nchunks = (J.ni + chunk - 1) / chunk;
   if (ctx->timing) {
     const bioem_status st = ensure_events(ctx, nchunks);
@@ -291,15 +303,18 @@ bioem_status run_job(bioem_ctx* ctx, Job& J, int prec) {
   for (int i0 = 0; i0 < J.ni; i0 += chunk) {
     const int cn = std::min(chunk, J.ni - i0);
     const LogpostArgs a = job_args(J, i0, cn, rec.as<bioem_erec>());
+    if (J.mf)
+      HIP_OR_FAIL(ctx, launch_mf_copy_at(s, a.ispec, J.table.as<float>(), cn, J.nc, J.nx, J.ny, at.as<float4>()));
     if (ctx->timing) HIP_OR_FAIL(ctx, hipEventRecord(ctx->ev_start[ctx->ev_used], s));
-    hipError_t e = split ? launch_logpost_split(s, a, prec == BIOEM_PREC_SPLIT_BF16, cfg.shape, cfg.ti, cfg.ts)
-                         : launch_logpost_f32(s, a);
+    hipError_t e = split  ? launch_logpost_split(s, a, prec == BIOEM_PREC_SPLIT_BF16, cfg.shape, cfg.ti, cfg.ts)
+                   : J.mf ? launch_logpost_mf32(s, a, at.as<float4>(), J.proj->mf, J.mftab.as<float4>(), J.ti, J.ts)
+                          : launch_logpost_f32(s, a);
     if (ctx->timing && e == hipSuccess) {
       HIP_OR_FAIL(ctx, hipEventRecord(ctx->ev_stop[ctx->ev_used], s));
       ++ctx->ev_used;
       ctx->timed_evals += (double)cn * J.nslots * J.nc;
     }
-    if (e == hipSuccess) e = finalize_chunk(s, J, a, i0, split);
+    if (e == hipSuccess) e = finalize_chunk(s, J, a, i0, split || J.mf);
     if (e != hipSuccess) return fail(ctx, BIOEM_EDEVICE, "bioem_logpost: launch failed: %s", hipGetErrorString(e));
   }
   return BIOEM_OK;
@@ -437,6 +452,7 @@ void bioem_free_proj(bioem_proj* p) {
   (void)hipSetDevice(p->device);
   if (p->spec) (void)hipFree(p->spec);
   if (p->tile) (void)hipFree(p->tile);
+  if (p->mf) (void)hipFree(p->mf);
   if (p->expo) (void)hipFree(p->expo);
   delete p;
 }
@@ -518,14 +534,15 @@ bioem_status bioem_project(bioem_ctx* ctx, const double* spheres, int32_t ns, co
   bioem_proj* p = new (std::nothrow) bioem_proj;
   if (!p) return fail(ctx, BIOEM_ENOMEM, "bioem_project: host allocation");
   p->n = nq; p->nx = nx; p->ny = ny; p->pixel = pixel_A; p->device = ctx->device;
-  const size_t tlen = tile_spec_len(nx, ny);
+  const size_t tlen = tile_spec_len(nx, ny), mlen = mf_len(nx, ny);
   hipError_t e = hipMalloc(reinterpret_cast<void**>(&p->spec), sizeof(float2) * slen * nq);
   if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&p->tile), sizeof(float4) * tlen * nq);
+  if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&p->mf), sizeof(float4) * mlen * nq);
   if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&p->expo), sizeof(int32_t) * nq);
   if (e != hipSuccess) {
     bioem_free_proj(p);
     return fail(ctx, BIOEM_ENOMEM, "bioem_project: device allocation of %zu MB failed",
-                ((sizeof(float2) * slen + sizeof(float4) * tlen) * nq) >> 20);
+                ((sizeof(float2) * slen + sizeof(float4) * (tlen + mlen)) * nq) >> 20);
   }
   const size_t per = (size_t)nx * ny * 8 + (size_t)ny * mh * 16 + len * 16;
   const int chunk = chunk_items(nq, per);
@@ -540,6 +557,7 @@ bioem_status bioem_project(bioem_ctx* ctx, const double* spheres, int32_t ns, co
     if (e == hipSuccess) e = launch_rdft2(s, i0.as<double>(), nullptr, cn, nx, ny, rows.as<double2>(), s64.as<double2>());
     if (e == hipSuccess) e = launch_spec_store(s, s64.as<double2>(), cn, nx, ny, p->spec + slen * q0, p->expo + q0);
     if (e == hipSuccess) e = launch_tile_spec(s, p->spec + slen * q0, cn, nx, ny, p->tile + tlen * q0);
+    if (e == hipSuccess) e = launch_mf_copy_spec(s, p->spec + slen * q0, cn, nx, ny, p->mf + mlen * q0);
   }
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   if (e != hipSuccess) {
@@ -663,15 +681,14 @@ bioem_status bioem_logpost(bioem_ctx* ctx, const bioem_proj* proj, const bioem_i
   if (!ctx) return BIOEM_EINVAL;
   bioem_opts o{};
   if (opts) o = *opts;
-  if (o.reserved[0] || o.reserved[1] || o.reserved[2] || o.reserved[3])
-    return fail(ctx, BIOEM_EINVAL, "bioem_logpost: opts.reserved must be zero");
+  if (o.reserved) return fail(ctx, BIOEM_EINVAL, "bioem_logpost: opts.reserved must be zero");
   bioem_job jb{};
   jb.proj = proj; jb.imgs = imgs; jb.ctf = ctf; jb.nc = nc; jb.ctf_mem = ctf_mem; jb.max_shift = max_shift;
   jb.k = o.k; jb.cand_q = o.cand_q; jb.cand_mem = o.cand_mem;
   jb.logp = logp; jb.best = best; jb.logp_orient = o.logp_orient;
   HIP_OR_FAIL(ctx, hipSetDevice(ctx->device));
   Job J;
-  bioem_status st = plan_job(ctx, jb, o.prec, o.out_mem, J, "bioem_logpost");
+  bioem_status st = plan_job(ctx, jb, o.prec, o.out_mem, J, "bioem_logpost", o.kernel, o.tile_images, o.tile_slots);
   if (st != BIOEM_OK) return st;
   st = run_job(ctx, J, o.prec);
   if (st != BIOEM_OK) return st;

@@ -43,6 +43,7 @@ struct bioem_proj {
   double pixel = 0.0;         // A per pixel (sets the CTF frequency scale)
   float2* spec = nullptr;     // [n][nx/2+1][spec_ld(ny)]
   float4* tile = nullptr;     // [n][tile_spec_len(nx, ny)]
+  float4* mf = nullptr;       // [n][mf_len(nx, ny)] orbit-order copy (FP32 matrix-core kernel)
   int32_t* expo = nullptr;    // [n]
   int device = 0;
 };
@@ -136,6 +137,23 @@ struct BatchJob {
 };
 hipError_t launch_logpost_batch(hipStream_t s, const BatchJob* jobs, int njobs, bool bf16);
 bool split_supported(int nx, int ny, int S);
+
+// Plain FP32 form on the FP32 matrix cores (factored transform).  Orbit-order
+// copies: mf_len(nx, ny) float4 per item; projections from stored spectra,
+// image x CTF products conj(F I_o) x table (item i * nc + c, DC zeroed).
+size_t mf_len(int nx, int ny);
+size_t mf32_smem_bytes(int nx, int ny);
+bool mf32_supported(int nx, int ny, int S);
+hipError_t launch_mf_copy_spec(hipStream_t s, const float2* spec, int n, int nx, int ny, float4* out);
+hipError_t launch_mf_copy_at(hipStream_t s, const float2* ispec, const float* table, int ni, int nc, int nx, int ny,
+                             float4* out);
+// Operand tables of one (box, shift window): mf32_table_len float4.
+size_t mf32_table_len(int nx, int ny);
+hipError_t launch_mf_tables(hipStream_t s, int nx, int ny, int S, float4* tabs);
+// a.rec receives one record per evaluation (d = -1: the best displacement is
+// recovered afterwards); ti, ts: item tile, 0 = default.
+hipError_t launch_logpost_mf32(hipStream_t s, const LogpostArgs& a, const float4* at, const float4* pm,
+                               const float4* tabs, int ti, int ts);
 
 // Per image: FP64 likelihood terms from the per-evaluation records, LSE over
 // orientations, CTF sets and shifts, best grid point, per-orientation LSE.

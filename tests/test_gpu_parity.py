@@ -14,8 +14,12 @@ TOL_NAT = 0.01   # per-image |delta log P| bar for the plain path
 # bar per transform mode: FP32 and the fp16 hi/lo split (about 22 significant
 # bits) meet the plain-path bar; the bf16 hi/lo split (about 16 bits) is the
 # precision form with the 0.1 nat bar.
-TOL = {"f32": 0.01, "split_f16": 0.01, "split_bf16": 0.1}
-PRECS = ["f32", "split_f16", "split_bf16"]
+TOL = {"f32": 0.01, "f32_valu": 0.01, "split_f16": 0.01, "split_bf16": 0.1}
+PRECS = ["f32", "f32_valu", "split_f16", "split_bf16"]
+# f32: the default plain form (FP32 matrix cores, factored transform);
+# f32_valu: the direct pruned transform on the vector ALUs (bioem_opts.kernel 2)
+KW = {"f32": dict(prec="f32"), "f32_valu": dict(prec="f32", kernel=2),
+      "split_f16": dict(prec="split_f16"), "split_bf16": dict(prec="split_bf16")}
 
 
 def _say(*a):
@@ -82,7 +86,7 @@ def test_config1_logpost_parity(P, ctx, cfg1, cfg1_oracle, prec):
     _say(f"config1 parity prec={prec}: 50 images x 100 q x 4 c, S=5")
     proj = P.project(ctx, wl.models[0], cls.quats, cls.nx, cls.ny, cls.pixel_A)
     im = P.prepare_images(ctx, imgs)
-    out = P.logpost(ctx, proj, im, cls.ctf, cls.max_shift, prec=prec, orient=True)
+    out = P.logpost(ctx, proj, im, cls.ctf, cls.max_shift, orient=True, **KW[prec])
     tol = TOL[prec]
     d = np.abs(out["logp"] - r.logp)
     _say(f"  max |dlogP| = {d.max():.3e}")
@@ -90,12 +94,13 @@ def test_config1_logpost_parity(P, ctx, cfg1, cfg1_oracle, prec):
     b = out["best"]
     assert np.all(b["status"] == 0)
     assert np.abs(b["logl"] - r.best_logl).max() <= tol
-    # the maximising grid point is unique here unless two values tie within tolerance
-    same = (b["q"] == r.best_q) & (b["c"] == r.best_c) & (b["dx"] == r.best_dx) & (b["dy"] == r.best_dy)
-    assert same.mean() >= 0.9
-    for i in np.nonzero(~same)[0]:
-        # a different argmax must still attain the maximum within tolerance
-        assert abs(b["logl"][i] - r.best_logl[i]) <= tol
+    # several grid points can attain the maximum within the tolerance: every
+    # reported point must attain it by the oracle's own likelihood there
+    for i in range(len(imgs)):
+        l_at = O.loglik_at(imgs[i], wl.models[0], cls.quats[b["q"][i]], cls.ctf[b["c"][i]], cls.pixel_A,
+                           b["dx"][i], b["dy"][i])
+        assert abs(l_at - r.best_logl[i]) <= tol, (i, l_at, r.best_logl[i])
+        assert abs(b["logl"][i] - l_at) <= tol, (i, b["logl"][i], l_at)
     do = np.abs(out["orient"] - r.logp_orient)
     _say(f"  max |dlogP(q)| = {do.max():.3e}")
     assert do.max() <= tol
@@ -111,7 +116,7 @@ def test_recovery_on_grid(P, ctx, prec):
                                     cls.pixel_A, 1.0, 0.0, rng.standard_normal((cls.ny, cls.nx)), 10.0)
                      for q, c, d in cases], dtype=np.float32)
     proj = P.project(ctx, wl.models[0], cls.quats, cls.nx, cls.ny, cls.pixel_A)
-    out = P.logpost(ctx, proj, P.prepare_images(ctx, imgs), cls.ctf, cls.max_shift, prec=prec)
+    out = P.logpost(ctx, proj, P.prepare_images(ctx, imgs), cls.ctf, cls.max_shift, **KW[prec])
     b = out["best"]
     for i, (q, c, d) in enumerate(cases):
         assert (b["q"][i], b["c"][i], b["dx"][i], b["dy"][i]) == (q, c, d[0], d[1])
@@ -132,7 +137,7 @@ def test_ragged_box_and_edges(P, ctx, prec):
     im = P.prepare_images(ctx, imgs)
     for S, ctf in [(0, cls.ctf[:1]), (3, cls.ctf), (12, cls.ctf[1:3])]:
         _say(f"ragged box {nx}x{ny} S={S} nc={len(ctf)} prec={prec}")
-        out = P.logpost(ctx, proj, im, ctf, S, orient=True, prec=prec)
+        out = P.logpost(ctx, proj, im, ctf, S, orient=True, **KW[prec])
         r = O.logpost_oracle(imgs[:3].astype(np.float64), wl.models[0], quats, ctf, pix, S, method="fft")
         assert np.abs(out["logp"][:3] - r.logp).max() <= TOL[prec]
         assert np.abs(out["orient"][:3] - r.logp_orient).max() <= TOL[prec]
@@ -148,7 +153,7 @@ def test_candidate_subset_matches_oracle(P, ctx, cfg1, prec):
     cand = np.stack([np.sort(rng.choice(100, 12, replace=False)) for _ in range(6)]).astype(np.int32)
     proj = P.project(ctx, wl.models[0], cls.quats, cls.nx, cls.ny, cls.pixel_A)
     out = P.logpost(ctx, proj, P.prepare_images(ctx, sub), cls.ctf, cls.max_shift, cand_q=cand,
-                    orient=True, prec=prec)
+                    orient=True, **KW[prec])
     for i in range(6):
         r = O.logpost_oracle(sub[i:i + 1].astype(np.float64), wl.models[0], cls.quats, cls.ctf,
                              cls.pixel_A, cls.max_shift, method="fft", q_subset=list(cand[i]))

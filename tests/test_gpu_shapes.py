@@ -10,7 +10,6 @@ arithmetic per evaluation; the compiler may contract the conjugate products
 into FMAs differently per variant, so shapes are compared with each other to
 a few 1e-4 nat rather than bitwise.
 """
-import os
 import sys
 
 import numpy as np
@@ -70,20 +69,25 @@ def cases(P, ctx):
 
 @pytest.mark.parametrize("prec", ["split_f16", "split_bf16"])
 def test_every_launch_shape_matches_oracle(P, ctx, cases, prec):
-    old = os.environ.get("BIOEM_SPLIT_SHAPE")
-    try:
-        for c in cases:
-            first = None
-            for shape in range(N_SHAPES):
-                os.environ["BIOEM_SPLIT_SHAPE"] = str(shape)
-                lp = P.logpost(ctx, c["proj"], c["imgs"], c["ctf"], c["S"], prec=prec)["logp"]
-                d = float(np.abs(lp - c["ref"]).max())
-                _say(f"{c['name']} {prec} shape {shape}: max |dlogP| vs oracle {d:.2e}")
-                assert d <= TOL[prec], (c["name"], shape, d)
-                first = lp if first is None else first
-                assert float(np.abs(lp - first).max()) <= SPREAD[prec], (c["name"], shape)
-    finally:
-        if old is None:
-            os.environ.pop("BIOEM_SPLIT_SHAPE", None)
-        else:
-            os.environ["BIOEM_SPLIT_SHAPE"] = old
+    for c in cases:
+        first = None
+        for shape in range(N_SHAPES):
+            lp = P.logpost(ctx, c["proj"], c["imgs"], c["ctf"], c["S"], prec=prec, kernel=shape + 1)["logp"]
+            d = float(np.abs(lp - c["ref"]).max())
+            _say(f"{c['name']} {prec} shape {shape}: max |dlogP| vs oracle {d:.2e}")
+            assert d <= TOL[prec], (c["name"], shape, d)
+            first = lp if first is None else first
+            assert float(np.abs(lp - first).max()) <= SPREAD[prec], (c["name"], shape)
+
+
+@pytest.mark.parametrize("tile", [None, (1, 1), (3, 5), (64, 64)])
+def test_f32_matrix_core_tiles_match_oracle(P, ctx, cases, tile):
+    """The FP32 matrix-core form under several item tiles (the tile only
+    reorders the work: results are bitwise the same)."""
+    for c in cases:
+        lp = P.logpost(ctx, c["proj"], c["imgs"], c["ctf"], c["S"], prec="f32", kernel=1, tile=tile)["logp"]
+        d = float(np.abs(lp - c["ref"]).max())
+        _say(f"{c['name']} f32 matrix cores tile {tile}: max |dlogP| vs oracle {d:.2e}")
+        assert d <= 0.01, (c["name"], tile, d)
+        ref = P.logpost(ctx, c["proj"], c["imgs"], c["ctf"], c["S"], prec="f32", kernel=1)["logp"]
+        assert np.array_equal(lp, ref)
