@@ -39,7 +39,6 @@ int chunk_items(int n, size_t per_item) {
 namespace {
 
 constexpr size_t kBatchRecordBudget = size_t(16) << 30;   // records of one persistent launch
-constexpr size_t kProductBudget = size_t(4) << 30;        // image x CTF copies per image chunk (FP32 form)
 
 // A validated bioem_logpost job with its device-side inputs, tables and
 // output staging.
@@ -61,7 +60,7 @@ struct Job {
   size_t len = 0;                  // stored spectrum stride
   int kernel = 0, ti = 0, ts = 0;  // bioem_opts kernel form and item tile (0 = default)
   bool mf = false;                 // F32 on the FP32 matrix cores
-  DevMem mftab;                    // its operand tables
+  DevMem mftab, mftm;              // its operand tables and orbit-order CTF tables
   Job() = default;
   Job(Job&&) = default;
 };
@@ -143,6 +142,8 @@ bioem_status plan_job(bioem_ctx* ctx, const bioem_job& jb, int prec, int out_mem
   if (mf) {
     HIP_OR_FAIL(ctx, J.mftab.alloc(sizeof(float4) * mf32_table_len(nx, ny)));
     HIP_OR_FAIL(ctx, launch_mf_tables(s, nx, ny, S, J.mftab.as<float4>()));
+    HIP_OR_FAIL(ctx, J.mftm.alloc(sizeof(float4) * mf_table_len(nx, ny) * nc));
+    HIP_OR_FAIL(ctx, launch_mf_copy_table(s, J.table.as<float>(), nc, nx, ny, J.mftm.as<float4>()));
   }
   HIP_OR_FAIL(ctx, launch_proj_norms(s, proj->spec, proj->expo, nq, J.table.as<float>(), nc, nx, ny,
                                      J.B.as<double>()));
@@ -289,12 +290,9 @@ bioem_status run_job(bioem_ctx* ctx, Job& J, int prec) {
     if (st != BIOEM_OK) return st;
   }
   const size_t per_image = sizeof(bioem_erec) * (size_t)J.nslots * J.nc;
-  int chunk = (int)std::max<size_t>(1, std::min<size_t>(J.ni, kRecordBudget / per_image));
-  const size_t at_image = sizeof(float4) * mf_len(J.nx, J.ny) * J.nc;
-  if (J.mf) chunk = (int)std::max<size_t>(1, std::min<size_t>(chunk, kProductBudget / at_image));
-  DevMem rec, at;
+  const int chunk = (int)std::max<size_t>(1, std::min<size_t>(J.ni, kRecordBudget / per_image));
+  DevMem rec;
   HIP_OR_FAIL(ctx, rec.alloc(per_image * chunk));
-  if (J.mf) HIP_OR_FAIL(ctx, at.alloc(at_image * chunk));
   const int nchunks = (J.ni + chunk - 1) / chunk;
   if (ctx->timing) {
     const bioem_status st = ensure_events(ctx, nchunks);
@@ -303,11 +301,10 @@ bioem_status run_job(bioem_ctx* ctx, Job& J, int prec) {
   for (int i0 = 0; i0 < J.ni; i0 += chunk) {
     const int cn = std::min(chunk, J.ni - i0);
     const LogpostArgs a = job_args(J, i0, cn, rec.as<bioem_erec>());
-    if (J.mf)
-      HIP_OR_FAIL(ctx, launch_mf_copy_at(s, a.ispec, J.table.as<float>(), cn, J.nc, J.nx, J.ny, at.as<float4>()));
     if (ctx->timing) HIP_OR_FAIL(ctx, hipEventRecord(ctx->ev_start[ctx->ev_used], s));
     hipError_t e = split  ? launch_logpost_split(s, a, prec == BIOEM_PREC_SPLIT_BF16, cfg.shape, cfg.ti, cfg.ts)
-                   : J.mf ? launch_logpost_mf32(s, a, at.as<float4>(), J.proj->mf, J.mftab.as<float4>(), J.ti, J.ts)
+                   : J.mf ? launch_logpost_mf32(s, a, J.imgs->mf + mf_len(J.nx, J.ny) * i0, J.proj->mf,
+                                                J.mftm.as<float4>(), J.mftab.as<float4>(), J.ti, J.ts)
                           : launch_logpost_f32(s, a);
     if (ctx->timing && e == hipSuccess) {
       HIP_OR_FAIL(ctx, hipEventRecord(ctx->ev_stop[ctx->ev_used], s));
@@ -462,6 +459,7 @@ void bioem_free_imgs(bioem_imgs* p) {
   (void)hipSetDevice(p->device);
   if (p->spec) (void)hipFree(p->spec);
   if (p->tile) (void)hipFree(p->tile);
+  if (p->mf) (void)hipFree(p->mf);
   if (p->expo) (void)hipFree(p->expo);
   if (p->stats) (void)hipFree(p->stats);
   delete p;
@@ -557,7 +555,7 @@ bioem_status bioem_project(bioem_ctx* ctx, const double* spheres, int32_t ns, co
     if (e == hipSuccess) e = launch_rdft2(s, i0.as<double>(), nullptr, cn, nx, ny, rows.as<double2>(), s64.as<double2>());
     if (e == hipSuccess) e = launch_spec_store(s, s64.as<double2>(), cn, nx, ny, p->spec + slen * q0, p->expo + q0);
     if (e == hipSuccess) e = launch_tile_spec(s, p->spec + slen * q0, cn, nx, ny, p->tile + tlen * q0);
-    if (e == hipSuccess) e = launch_mf_copy_spec(s, p->spec + slen * q0, cn, nx, ny, p->mf + mlen * q0);
+    if (e == hipSuccess) e = launch_mf_copy_spec(s, p->spec + slen * q0, cn, nx, ny, false, p->mf + mlen * q0);
   }
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   if (e != hipSuccess) {
@@ -585,9 +583,10 @@ bioem_status bioem_prepare_images(bioem_ctx* ctx, const float* imgs, int32_t ni,
   bioem_imgs* p = new (std::nothrow) bioem_imgs;
   if (!p) return fail(ctx, BIOEM_ENOMEM, "bioem_prepare_images: host allocation");
   p->n = ni; p->nx = nx; p->ny = ny; p->device = ctx->device;
-  const size_t tlen = tile_spec_len(nx, ny);
+  const size_t tlen = tile_spec_len(nx, ny), mlen = mf_len(nx, ny);
   hipError_t e = hipMalloc(reinterpret_cast<void**>(&p->spec), sizeof(float2) * slen * ni);
   if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&p->tile), sizeof(float4) * tlen * ni);
+  if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&p->mf), sizeof(float4) * mlen * ni);
   if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&p->expo), sizeof(int32_t) * ni);
   if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&p->stats), sizeof(double) * 3 * ni);
   if (e != hipSuccess) {
@@ -611,6 +610,7 @@ bioem_status bioem_prepare_images(bioem_ctx* ctx, const float* imgs, int32_t ni,
     if (e == hipSuccess) e = launch_rdft2(s, nullptr, src, cn, nx, ny, rows.as<double2>(), s64.as<double2>());
     if (e == hipSuccess) e = launch_spec_store(s, s64.as<double2>(), cn, nx, ny, p->spec + slen * i0, p->expo + i0);
     if (e == hipSuccess) e = launch_tile_spec(s, p->spec + slen * i0, cn, nx, ny, p->tile + tlen * i0);
+    if (e == hipSuccess) e = launch_mf_copy_spec(s, p->spec + slen * i0, cn, nx, ny, true, p->mf + mlen * i0);
     if (e == hipSuccess && in_mem == BIOEM_MEM_HOST) e = hipStreamSynchronize(s);  // stage reuse
   }
   if (e == hipSuccess) e = hipStreamSynchronize(s);

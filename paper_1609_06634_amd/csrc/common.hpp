@@ -52,6 +52,7 @@ struct bioem_imgs {
   int32_t n = 0, nx = 0, ny = 0;
   float2* spec = nullptr;     // [n][nx/2+1][spec_ld(ny)]
   float4* tile = nullptr;     // [n][tile_spec_len(nx, ny)]
+  float4* mf = nullptr;       // [n][mf_len(nx, ny)] orbit-order copy, DC zeroed (FP32 matrix-core kernel)
   int32_t* expo = nullptr;    // [n]
   double* stats = nullptr;    // [n][3]: C_o, C_oo, A
   int device = 0;
@@ -139,21 +140,23 @@ hipError_t launch_logpost_batch(hipStream_t s, const BatchJob* jobs, int njobs, 
 bool split_supported(int nx, int ny, int S);
 
 // Plain FP32 form on the FP32 matrix cores (factored transform).  Orbit-order
-// copies: mf_len(nx, ny) float4 per item; projections from stored spectra,
-// image x CTF products conj(F I_o) x table (item i * nc + c, DC zeroed).
+// copies: mf_len(nx, ny) float4 per spectrum (images with the DC coefficient
+// zeroed), mf_table_len(nx, ny) float4 per CTF table.
 size_t mf_len(int nx, int ny);
+size_t mf_table_len(int nx, int ny);
 size_t mf32_smem_bytes(int nx, int ny);
 bool mf32_supported(int nx, int ny, int S);
-hipError_t launch_mf_copy_spec(hipStream_t s, const float2* spec, int n, int nx, int ny, float4* out);
-hipError_t launch_mf_copy_at(hipStream_t s, const float2* ispec, const float* table, int ni, int nc, int nx, int ny,
-                             float4* out);
+hipError_t launch_mf_copy_spec(hipStream_t s, const float2* spec, int n, int nx, int ny, bool zero_dc,
+                               float4* out);
+hipError_t launch_mf_copy_table(hipStream_t s, const float* table, int nc, int nx, int ny, float4* out);
 // Operand tables of one (box, shift window): mf32_table_len float4.
 size_t mf32_table_len(int nx, int ny);
 hipError_t launch_mf_tables(hipStream_t s, int nx, int ny, int S, float4* tabs);
 // a.rec receives one record per evaluation (d = -1: the best displacement is
-// recovered afterwards); ti, ts: item tile, 0 = default.
-hipError_t launch_logpost_mf32(hipStream_t s, const LogpostArgs& a, const float4* at, const float4* pm,
-                               const float4* tabs, int ti, int ts);
+// recovered afterwards); im: the chunk's image copies; ti, ts: item tile
+// (images x orientation slots), 0 = default.
+hipError_t launch_logpost_mf32(hipStream_t s, const LogpostArgs& a, const float4* im, const float4* pm,
+                               const float4* tm, const float4* tabs, int ti, int ts);
 
 // Per image: FP64 likelihood terms from the per-evaluation records, LSE over
 // orientations, CTF sets and shifts, best grid point, per-orientation LSE.

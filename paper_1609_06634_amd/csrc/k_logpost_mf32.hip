@@ -126,8 +126,11 @@ __device__ inline void mf_where(const MfGeom& G, int w, int& col, int& r0, int& 
   r1 = col < 0 ? -1 : mf_row(G, j, 2 * half + 1);
 }
 
+// Orbit-order copy of stored spectra (images with zero_dc: the (0, 0)
+// coefficient is set to zero, so the product with any projection has no DC
+// term and the offset mu is integrated out exactly).
 __global__ __launch_bounds__(256) void k_mf_copy_spec(const float2* __restrict__ spec, long total, int nx, int ny,
-                                                      float4* __restrict__ out) {
+                                                      int zero_dc, float4* __restrict__ out) {
   const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= total) return;
   const MfGeom G = mf_geom(nx, ny);
@@ -138,33 +141,49 @@ __global__ __launch_bounds__(256) void k_mf_copy_spec(const float2* __restrict__
   float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
   if (col >= 0) {
     const float2* c = spec + (size_t)item * (nx / 2 + 1) * spec_ld(ny) + (size_t)col * spec_ld(ny);
-    if (r0 >= 0) { v.x = c[r0].x; v.y = c[r0].y; }
-    if (r1 >= 0) { v.z = c[r1].x; v.w = c[r1].y; }
+    if (r0 >= 0 && !(zero_dc && col == 0 && r0 == 0)) { v.x = c[r0].x; v.y = c[r0].y; }
+    if (r1 >= 0 && !(zero_dc && col == 0 && r1 == 0)) { v.z = c[r1].x; v.w = c[r1].y; }
   }
   out[idx] = v;
 }
 
-// conj(F I_o) x CTF table for images [0, ni) x CTF sets [0, nc), item i * nc + c;
-// the (0, 0) coefficient is set to zero (the offset mu is integrated out).
-__global__ __launch_bounds__(256) void k_mf_copy_at(const float2* __restrict__ ispec, const float* __restrict__ table,
-                                                    long total, int nc, int nx, int ny, float4* __restrict__ out) {
+// Orbit-order copy of the CTF x envelope tables: for each (half group,
+// K-step, lane) the four values T(j), T(H-j), T(H+j), T(N-j) of the lane's
+// column (one float4), then the packed slot's second column [KS1][4].
+__host__ __device__ inline size_t mf_tab_len(const MfGeom& G) {
+  return (size_t)G.nHG * G.KS1 * 64 + (size_t)G.KS1 * 4;
+}
+
+__global__ __launch_bounds__(256) void k_mf_copy_table(const float* __restrict__ table, long total, int nx, int ny,
+                                                       float4* __restrict__ out) {
   const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= total) return;
   const MfGeom G = mf_geom(nx, ny);
-  const long per = (long)mf_item_len(G);
+  const long per = (long)mf_tab_len(G);
   const long item = idx / per;
-  const long i = item / nc, c = item - i * nc;
-  int col, r0, r1;
-  mf_where(G, (int)(idx - item * per), col, r0, r1);
-  float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-  if (col >= 0) {
-    const size_t ld = spec_ld(ny), clen = (size_t)(nx / 2 + 1) * ld;
-    const float2* o = ispec + (size_t)i * clen + (size_t)col * ld;
-    const float* t = table + (size_t)c * clen + (size_t)col * ld;
-    if (r0 >= 0 && !(col == 0 && r0 == 0)) { v.x = o[r0].x * t[r0]; v.y = -o[r0].y * t[r0]; }
-    if (r1 >= 0 && !(col == 0 && r1 == 0)) { v.z = o[r1].x * t[r1]; v.w = -o[r1].y * t[r1]; }
+  const int w = (int)(idx - item * per), ml = G.nHG * G.KS1 * 64;
+  int col, j;
+  if (w < ml) {
+    const int lane = w & 63, step = w >> 6;
+    const int h = step / G.KS1, s1 = step - h * G.KS1;
+    col = mf_col(G, h, lane & 15);
+    if (col == -2) col = 0;
+    j = 4 * s1 + (lane >> 4);
+  } else {
+    const int w2 = w - ml;
+    col = G.Mx;
+    j = 4 * (w2 >> 2) + (w2 & 3);
   }
-  out[idx] = v;
+  float v[4] = {0.f, 0.f, 0.f, 0.f};
+  if (col >= 0) {
+    const float* c = table + (size_t)item * (nx / 2 + 1) * spec_ld(ny) + (size_t)col * spec_ld(ny);
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int r = mf_row(G, j, e);
+      if (r >= 0) v[e] = c[r];
+    }
+  }
+  out[idx] = make_float4(v[0], v[1], v[2], v[3]);
 }
 
 // Matrix-core operand tables, built in FP64 and rounded once:
@@ -222,22 +241,27 @@ __global__ __launch_bounds__(256) void k_mf_tables(int nx, int ny, int S, float4
 }
 
 struct MfArgs {
-  LogpostArgs a;
-  const float4* at;   // [ni][nc][len] image x CTF products (chunk-relative images)
-  const float4* pm;   // [nq][len] projections
-  const float4* F1;   // [KS1][64]
-  const float4* F2;   // [nHG][2][64]
+  const float4* im;     // [ni][len] image spectra, orbit order (chunk-relative images)
+  const float4* pm;     // [nq][len] projection spectra, orbit order
+  const float4* tm;     // [nc][tlen] CTF x envelope tables, orbit order
+  const float4* F1;     // [KS1][64]
+  const float4* F2;     // [nHG][2][64]
+  const double* istats; const int32_t* iexpo; const int32_t* pexpo; const double* B;
+  const int32_t* cand;  // [ni][k] or null
+  bioem_erec* rec;      // [ni][nslots][nc]
+  double kscale;
+  long len, tlen;
+  int ni, nq, nc, k, nx, ny, S;
   int KS1, nHG;
-  long len;           // float4 per item
-  int ti, ts, n_ti, n_ts;   // item tile: images x orientation slots
+  int G, wpp, R, passes;        // pairs per group, waves per pair, K-steps per round, CTF passes
+  int ti, ts, n_ti, n_ts;       // pair tile: images x orientation slots
 };
+
+constexpr int kMfWaves = 8;     // one workgroup per CU, two waves per SIMD
+constexpr int kSlotF4 = 136;    // one produced K-step in LDS: [2][64 lanes] float4 + [2][4] (packed column)
 
 __device__ __forceinline__ f4 mma(float a, float b, f4 c) {
   return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
-}
-
-__device__ __forceinline__ float2 cmul(float ar, float ai, float br, float bi) {
-  return make_float2(fmaf(ar, br, -ai * bi), fmaf(ar, bi, ai * br));
 }
 
 __device__ __forceinline__ float wmax_f(float v) {
@@ -259,246 +283,412 @@ __device__ __forceinline__ float log1p_f(float u) {
   return d == 0.0f ? u : __logf(w) * (u / d);
 }
 
-struct Step {
-  float4 a0, a1, p0, p1;
+// conj(a) b for the complex pairs (a.xy, b.xy) and (a.zw, b.zw).
+__device__ __forceinline__ float4 cjmul2(float4 a, float4 b) {
+  return make_float4(fmaf(a.x, b.x, a.y * b.y), fmaf(a.x, b.y, -a.y * b.x), fmaf(a.z, b.z, a.w * b.w),
+                     fmaf(a.z, b.w, -a.w * b.z));
+}
+
+// Folded products of one orbit, W_e = conj(I_e) P_e (e = 0..3 over j, H-j,
+// H+j, N-j):  (W0 + W3, W0 - W3), (W1 + W2, W1 - W2); for the shared slot
+// (points 0, N/4, H, 3N/4): (W0, W2), (W1 + W3, W1 - W3).
+__device__ __forceinline__ void fold_w(float4 i0, float4 i1, float4 p0, float4 p1, float4& o0, float4& o1) {
+  const float4 w01 = cjmul2(i0, p0), w23 = cjmul2(i1, p1);
+  o0 = make_float4(w01.x + w23.z, w01.y + w23.w, w01.x - w23.z, w01.y - w23.w);
+  o1 = make_float4(w01.z + w23.x, w01.w + w23.y, w01.z - w23.x, w01.w - w23.y);
+}
+
+__device__ __forceinline__ void fold_w_special(float4 i0, float4 i1, float4 p0, float4 p1, float4& o0,
+                                               float4& o1) {
+  const float4 w01 = cjmul2(i0, p0), w23 = cjmul2(i1, p1);
+  o0 = make_float4(w01.x, w01.y, w23.x, w23.y);
+  o1 = make_float4(w01.z + w23.z, w01.w + w23.w, w01.z - w23.z, w01.w - w23.w);
+}
+
+// Block operands (u0, v0, u1, v1) of one column from its folded products X
+// and CTF values T of the orbit.  Regular slot: with A+- = X0, B+- = X1 and
+// T(j) = T(N-j) = Ta, T(H-j) = T(H+j) = Tb (the envelope is radial):
+//   u0 = Ta A+ + Tb B+,  u1 = Ta A+ - Tb B+,  v0 = Ta A- - Tb B-,  v1 = Ta A- + Tb B-.
+// Shared slot: u0 = T0 W0 + TH W2, u1 = T0 W0 - TH W2, v0 = 0,
+// v1 = TQ (W1 - W3), and c = TQ (W1 + W3) is added to the even rows later.
+struct Ops {
+  float u0r, u0i, v0r, v0i, u1r, u1i, v1r, v1i;
 };
 
-__device__ __forceinline__ void load_step(Step& st, const float4* __restrict__ A, const float4* __restrict__ P,
-                                          int t, int lane) {
-  const size_t o = ((size_t)t * 64 + lane) * 2;
-  st.a0 = A[o];
-  st.a1 = A[o + 1];
-  st.p0 = P[o];
-  st.p1 = P[o + 1];
+__device__ __forceinline__ Ops ops_regular(float4 x0, float4 x1, float4 t) {
+  const float ta = t.x, tb = t.y;
+  const float ypr = tb * x1.x, ypi = tb * x1.y, ymr = tb * x1.z, ymi = tb * x1.w;
+  Ops o;
+  o.u0r = fmaf(ta, x0.x, ypr); o.u0i = fmaf(ta, x0.y, ypi);
+  o.u1r = fmaf(ta, x0.x, -ypr); o.u1i = fmaf(ta, x0.y, -ypi);
+  o.v0r = fmaf(ta, x0.z, -ymr); o.v0i = fmaf(ta, x0.w, -ymi);
+  o.v1r = fmaf(ta, x0.z, ymr); o.v1i = fmaf(ta, x0.w, ymi);
+  return o;
 }
 
-// One evaluation (image i, orientation slot, CTF set c) by one wave.
-__device__ __forceinline__ void mf_item(const MfArgs& ma, const float4* __restrict__ F1s,
-                                        const float4* __restrict__ F2s, int item) {
-  const LogpostArgs& a = ma.a;
-  const int lane = threadIdx.x & 63, p = lane & 15, g = lane >> 4;
-  const int nslots = a.cand ? a.k : a.nq, nc = a.nc;
-  const int tile_items = ma.ti * ma.ts * nc;
-  const int tile = item / tile_items, rr = item - tile * tile_items;
-  const int ti = tile / ma.n_ts, ts = tile - ti * ma.n_ts;
-  const int c = rr % nc, pr = rr / nc;
-  const int i = ti * ma.ti + pr / ma.ts;
-  const int slot = ts * ma.ts + pr % ma.ts;
-  if (i >= a.ni || slot >= nslots) return;   // uniform across the wave
-  const int q = a.cand ? a.cand[(size_t)i * a.k + slot] : slot;
-  bioem_erec* out = a.rec + ((size_t)i * nslots + slot) * nc + c;
-  const double A = a.istats[3 * i + 2];
-  const double B = a.B[(size_t)q * nc + c];
-  if (!(A > 0.0) || !(B > 0.0)) {   // degenerate image or projection: void evaluation
-    if (lane == 0) *out = bioem_erec{-1.0f, 0.0f, -1, 0};
-    return;
-  }
-  const int S = a.S;
-  const int KS1 = ma.KS1, nHG = ma.nHG, nsteps = KS1 * nHG;
-  const float4* Ab = ma.at + ((size_t)i * nc + c) * ma.len;
-  const float4* Pb = ma.pm + (size_t)q * ma.len;
-  const size_t side = (size_t)nHG * KS1 * 128;
-
-  f4 d2[2][8];
-#pragma unroll
-  for (int s = 0; s < 2; ++s)
-#pragma unroll
-    for (int t = 0; t < 8; ++t) d2[s][t] = f4{0.f, 0.f, 0.f, 0.f};
-
-  Step cur;
-  load_step(cur, Ab, Pb, 0, lane);
-  for (int h = 0; h < nHG; ++h) {
-    f4 d1[2][4];
-#pragma unroll
-    for (int t = 0; t < 2; ++t)
-#pragma unroll
-      for (int b = 0; b < 4; ++b) d1[t][b] = f4{0.f, 0.f, 0.f, 0.f};
-    float cre = 0.f, cim = 0.f;   // Z(N/4) + Z(3N/4) of this lane's column (slot 0)
-    for (int s1 = 0; s1 < KS1; ++s1) {
-      const int t = h * KS1 + s1;
-      Step nxt;
-      if (t + 1 < nsteps) load_step(nxt, Ab, Pb, t + 1, lane);
-      float2 e0 = cmul(cur.a0.x, cur.a0.y, cur.p0.x, cur.p0.y);
-      float2 e1 = cmul(cur.a0.z, cur.a0.w, cur.p0.z, cur.p0.w);
-      float2 e2 = cmul(cur.a1.x, cur.a1.y, cur.p1.x, cur.p1.y);
-      float2 e3 = cmul(cur.a1.z, cur.a1.w, cur.p1.z, cur.p1.w);
-      if (h == 0) {      // uniform
-        if (p == 0) {    // packed slot: + i Z(l, M)
-          const size_t o = side + ((size_t)s1 * 4 + g) * 2;
-          const float4 sa0 = Ab[o], sa1 = Ab[o + 1], sp0 = Pb[o], sp1 = Pb[o + 1];
-          const float2 f0 = cmul(sa0.x, sa0.y, sp0.x, sp0.y);
-          const float2 f1 = cmul(sa0.z, sa0.w, sp0.z, sp0.w);
-          const float2 f2 = cmul(sa1.x, sa1.y, sp1.x, sp1.y);
-          const float2 f3 = cmul(sa1.z, sa1.w, sp1.z, sp1.w);
-          e0.x -= f0.y; e0.y += f0.x;
-          e1.x -= f1.y; e1.y += f1.x;
-          e2.x -= f2.y; e2.y += f2.x;
-          e3.x -= f3.y; e3.y += f3.x;
-        }
-      }
-      const float z0ar = e0.x + e2.x, z0ai = e0.y + e2.y, z1ar = e0.x - e2.x, z1ai = e0.y - e2.y;
-      const float z0br = e1.x + e3.x, z0bi = e1.y + e3.y, z1br = e1.x - e3.x, z1bi = e1.y - e3.y;
-      float u0r = z0ar + z0br, u0i = z0ai + z0bi, v0r = z0ar - z0br, v0i = z0ai - z0bi;
-      float u1r = z1ar - z1br, u1i = z1ai - z1bi, v1r = z1ar + z1br, v1i = z1ai + z1bi;
-      if (s1 == 0) {   // uniform: slot 0 (lanes g = 0) holds the points 0, N/4, H, 3N/4
-        if (g == 0) {
-          u0r = z0ar; u0i = z0ai;
-          v0r = 0.f; v0i = 0.f;
-          u1r = z1ar; u1i = z1ai;
-          v1r = z1br; v1i = z1bi;
-          cre = z0br; cim = z0bi;
-        }
-      }
-      const float4 Bf = F1s[s1 * 64 + lane];
-      d1[0][0] = mma(u0r, Bf.x, d1[0][0]);
-      d1[1][0] = mma(u0i, Bf.x, d1[1][0]);
-      d1[0][1] = mma(v0r, Bf.y, d1[0][1]);
-      d1[1][1] = mma(v0i, Bf.y, d1[1][1]);
-      d1[0][2] = mma(u1r, Bf.z, d1[0][2]);
-      d1[1][2] = mma(u1i, Bf.z, d1[1][2]);
-      d1[0][3] = mma(v1r, Bf.w, d1[0][3]);
-      d1[1][3] = mma(v1i, Bf.w, d1[1][3]);
-      if (t + 1 < nsteps) cur = nxt;
-    }
-    // even rows: + (-1)^p (Z(N/4) + Z(3N/4)) of each column (slot 0, lane = data row)
-    {
-      const float sg = (p & 1) ? -1.0f : 1.0f;
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const float xr = __shfl(cre, 4 * g + r, 64), xi = __shfl(cim, 4 * g + r, 64);
-        d1[0][0][r] = fmaf(sg, xr, d1[0][0][r]);
-        d1[1][0][r] = fmaf(sg, xi, d1[1][0][r]);
-      }
-    }
-    // stage 2: the accumulator rows 4g + r are (pair 2g + r/2, member r%2)
-#pragma unroll
-    for (int s = 0; s < 2; ++s) {
-      const f4 Ur = d1[0][2 * s], Ui = d1[1][2 * s], Vr = d1[0][2 * s + 1], Vi = d1[1][2 * s + 1];
-      float a0u = 0.f, a0v = 0.f;
-#pragma unroll
-      for (int h2 = 0; h2 < 2; ++h2) {
-        const int ra = 2 * h2, rb = 2 * h2 + 1;
-        float URp = Ur[ra] + Ur[rb], URm = Ur[ra] - Ur[rb], UIp = Ui[ra] + Ui[rb], UIm = Ui[ra] - Ui[rb];
-        float VRp = Vr[ra] + Vr[rb], VRm = Vr[ra] - Vr[rb], VIp = Vi[ra] + Vi[rb], VIm = Vi[ra] - Vi[rb];
-        if (h == 0 && h2 == 0) {   // uniform
-          if (g == 0) {            // pair 0: packed slot (member 0) and column M/2 (member 1)
-            a0u = Ur[ra] + Ui[ra];
-            a0v = Vi[ra] - Vr[ra];
-            URm = Ur[ra] - Ui[ra];
-            VIm = Vi[ra] + Vr[ra];
-            URp = Ur[rb];
-            VIp = Vi[rb];
-            UIp = Ui[rb];
-            VRp = Vr[rb];
-            UIm = 0.f;
-            VRm = 0.f;
-          }
-        }
-        const float4 Af = F2s[(h * 2 + h2) * 64 + lane];
-        d2[s][0] = mma(Af.x, URp, d2[s][0]);
-        d2[s][1] = mma(Af.x, VIp, d2[s][1]);
-        d2[s][2] = mma(Af.y, UIm, d2[s][2]);
-        d2[s][3] = mma(Af.y, VRm, d2[s][3]);
-        d2[s][4] = mma(Af.z, URm, d2[s][4]);
-        d2[s][5] = mma(Af.z, VIm, d2[s][5]);
-        d2[s][6] = mma(Af.w, UIp, d2[s][6]);
-        d2[s][7] = mma(Af.w, VRp, d2[s][7]);
-      }
-      if (h == 0) {   // a(0) = Y(0) + Y(M), weight 1 at every even dx
-        const float xu = __shfl(a0u, p, 64), xv = __shfl(a0v, p, 64);
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          d2[s][0][r] += xu;
-          d2[s][1][r] += xv;
-        }
-      }
-    }
-  }
-
-  // epilogue: X at (+-k, +-dx) from the eight stage-2 products, squared
-  // (-1 marks slots outside the window and the duplicates of k = 0, dx = 0)
-  float x2max = 0.0f;
-#pragma unroll
-  for (int s = 0; s < 2; ++s) {
-    const int k = 2 * p + s;
-    const bool kp = k <= S, km = kp && k > 0;
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int rho = 4 * g + r;
-      const bool ap = 2 * rho <= S, am = ap && rho > 0, bp = 2 * rho + 1 <= S;
-      const float Eap = d2[s][0][r] - d2[s][1][r], Eam = d2[s][0][r] + d2[s][1][r];
-      const float Oap = d2[s][2][r] + d2[s][3][r], Oam = d2[s][2][r] - d2[s][3][r];
-      const float Ebp = d2[s][4][r] - d2[s][5][r], Ebm = d2[s][4][r] + d2[s][5][r];
-      const float Obp = d2[s][6][r] + d2[s][7][r], Obm = d2[s][6][r] - d2[s][7][r];
-      float x[8];
-      x[0] = Eap - Oap; x[1] = Eap + Oap; x[2] = Eam - Oam; x[3] = Eam + Oam;
-      x[4] = Ebp - Obp; x[5] = Ebp + Obp; x[6] = Ebm - Obm; x[7] = Ebm + Obm;
-      const bool ok[8] = {kp && ap, kp && am, km && ap, km && am, kp && bp, kp && bp, km && bp, km && bp};
-#pragma unroll
-      for (int v = 0; v < 8; ++v) {
-        const float x2 = ok[v] ? x[v] * x[v] : -1.0f;
-        d2[s][v][r] = x2;
-        x2max = fmaxf(x2max, x2);
-      }
-    }
-  }
-  const float wmax = wmax_f(x2max);
-  const int esc = 2 * (a.iexpo[i] + a.pexpo[q]);
-  const double kappa = ldexp(a.kscale / (A * B), esc);
-  const double rho2 = fmin((double)wmax * kappa, 1.0 - 0x1p-52);
-  const float cu = (float)(kappa / (1.0 - rho2));
-  const float base = wmax * cu;
-  const double n = (double)a.nx * a.ny;
-  const float c2 = (float)(0.5 * n - 1.0);
-  float sum = 0.0f;
-  if (c2 >= 1024.0f) {
-    // log1p(u) by its degree-3 series on [0, 0.05]; terms with u >= 0.05 are
-    // below e^-50 of the maximum term (1) and are left at u = 0.05
-    const float c2l2e = c2 * 1.4426950408889634f;
-    const float p1 = -c2l2e, p2 = 0.5f * c2l2e, p3 = -c2l2e / 3.0f;
-#pragma unroll
-    for (int s = 0; s < 2; ++s)
-#pragma unroll
-      for (int v = 0; v < 8; ++v)
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const float x2 = d2[s][v][r];
-          const float u = __builtin_amdgcn_fmed3f(fmaf(-x2, cu, base), 0.0f, 0.05f);
-          const float t = __builtin_amdgcn_exp2f(u * (p1 + u * (p2 + u * p3)));
-          sum += x2 >= 0.0f ? t : 0.0f;
-        }
-  } else {
-#pragma unroll
-    for (int s = 0; s < 2; ++s)
-#pragma unroll
-      for (int v = 0; v < 8; ++v)
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const float x2 = d2[s][v][r];
-          const float u = fmaxf(fmaf(-x2, cu, base), 0.0f);
-          const float t = __expf(-c2 * log1p_f(u));
-          sum += x2 >= 0.0f ? t : 0.0f;
-        }
-  }
-  const float tot = wsum_f(sum);
-  if (lane == 0) *out = bioem_erec{wmax, tot, -1, 0};
+__device__ __forceinline__ Ops ops_special(float4 x0, float4 x1, float4 t, float& cr, float& ci) {
+  const float t0 = t.x, tq = t.y, th = t.z;
+  const float yr = th * x0.z, yi = th * x0.w;
+  Ops o;
+  o.u0r = fmaf(t0, x0.x, yr); o.u0i = fmaf(t0, x0.y, yi);
+  o.u1r = fmaf(t0, x0.x, -yr); o.u1i = fmaf(t0, x0.y, -yi);
+  o.v0r = 0.f; o.v0i = 0.f;
+  o.v1r = tq * x1.z; o.v1i = tq * x1.w;
+  cr = tq * x1.x; ci = tq * x1.y;
+  return o;
 }
 
-template <int WAVES>
-__global__ __launch_bounds__(64 * WAVES) void k_logpost_mf32(MfArgs ma) {
+// One workgroup: groups of G (image, orientation) pairs; wave w scores CTF set
+// pass * wpp + w % wpp of pair w / wpp.  The folded products conj(I) P of each
+// K-step are made once per pair (each wave makes one K-step of a round) and
+// read by the pair's waves from LDS; every wave then applies its own CTF set.
+__global__ __launch_bounds__(64 * kMfWaves) void k_logpost_mf32(MfArgs ma) {
   extern __shared__ float4 lds_mf[];
   const int n1 = ma.KS1 * 64, n2 = ma.nHG * 128;
-  for (int e = threadIdx.x; e < n1 + n2; e += 64 * WAVES) lds_mf[e] = e < n1 ? ma.F1[e] : ma.F2[e - n1];
+  float4* const F1s = lds_mf;
+  float4* const F2s = lds_mf + n1;
+  float4* const slots = F2s + n2;                          // [2][8][kSlotF4]
+  float4* const stage = slots + 2 * 8 * kSlotF4;           // [8 waves][16]
+  for (int e = threadIdx.x; e < n1 + n2; e += 64 * kMfWaves) lds_mf[e] = e < n1 ? ma.F1[e] : ma.F2[e - n1];
   __syncthreads();
-  const long n_items = (long)ma.n_ti * ma.n_ts * ma.ti * ma.ts * ma.a.nc;
-  const int wave = blockIdx.x * WAVES + (threadIdx.x >> 6);
-  const int nwaves = gridDim.x * WAVES;
-  for (long item = wave; item < n_items; item += nwaves) mf_item(ma, lds_mf, lds_mf + n1, (int)item);
+
+  const int lane = threadIdx.x & 63, p = lane & 15, g = lane >> 4;
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int KS1 = ma.KS1, nHG = ma.nHG, nsteps = KS1 * nHG;
+  const int G = ma.G, wpp = ma.wpp, R = ma.R, passes = ma.passes;
+  const int nrounds = (nsteps + R - 1) / R;
+  const int nslots = ma.cand ? ma.k : ma.nq;
+  const int S = ma.S;
+  const size_t main_len = (size_t)nHG * KS1 * 128, tmain = (size_t)nHG * KS1 * 64;
+  // producer role: K-step w % R of each round for pair w / R of the group
+  const int gp_p = w / R, kp = w - gp_p * R;
+  // consumer role
+  const int gi = w / wpp, cw = w - gi * wpp;
+
+  const int tile_pairs = ma.ti * ma.ts;
+  const int groups_per_tile = (tile_pairs + G - 1) / G * passes;
+  const int n_tiles = ma.n_ti * ma.n_ts;
+  // tiles are dealt to the XCDs (workgroups go round-robin over the 8 XCDs),
+  // so one tile's images stay in one L2 while its orientations stream through
+  const int kx = min(8, (int)gridDim.x);
+  const int xcd = blockIdx.x % kx, lw = blockIdx.x / kx;
+  const int nwx = ((int)gridDim.x - xcd + kx - 1) / kx;
+
+  for (int t = xcd; t < n_tiles; t += kx) {
+    const int tI = t / ma.n_ts, tS = t - tI * ma.n_ts;
+    for (int gg = lw; gg < groups_per_tile; gg += nwx) {
+      const int pass = gg % passes, grp = gg / passes;
+      // pair (image, slot) of group member m, valid or not
+      auto pair_of = [&](int m, int& i, int& slot) -> bool {
+        const int pl = grp * G + m;
+        i = tI * ma.ti + pl % ma.ti;
+        slot = tS * ma.ts + pl / ma.ti;
+        return pl < tile_pairs && i < ma.ni && slot < nslots;
+      };
+      // the group's first valid pair stands in for its invalid members (a
+      // group can begin past the last image of a tile row and still hold
+      // valid pairs); a group with none is skipped (uniform)
+      int i0 = 0, s0 = 0, m0 = -1;
+      for (int m = 0; m < G && m0 < 0; ++m)
+        if (pair_of(m, i0, s0)) m0 = m;
+      if (m0 < 0) continue;
+      int ip, sp, ic, sc;
+      if (!pair_of(gp_p, ip, sp)) { ip = i0; sp = s0; }
+      const bool cvalid_pair = pair_of(gi, ic, sc);
+      if (!cvalid_pair) { ic = i0; sc = s0; }
+      const int c = pass * wpp + cw;
+      const bool mine = cvalid_pair && c < ma.nc;
+      const int cc = min(c, ma.nc - 1);
+      const int qp = ma.cand ? ma.cand[(size_t)ip * ma.k + sp] : sp;
+      const int qc = ma.cand ? ma.cand[(size_t)ic * ma.k + sc] : sc;
+      const float4* Ib = ma.im + (size_t)ip * ma.len;
+      const float4* Pb = ma.pm + (size_t)qp * ma.len;
+      const float4* Tb = ma.tm + (size_t)cc * ma.tlen;
+
+      // producer: loads of one K-step (and the packed slot's second column,
+      // one float4 per lane of the first 16), then its folded products
+      float4 pf0, pf1, pf2, pf3, pfs;
+      auto load = [&](int rr) {
+        const int st = rr * R + kp;
+        if (st < nsteps) {
+          const size_t o = ((size_t)st * 64 + lane) * 2;
+          pf0 = Ib[o]; pf1 = Ib[o + 1]; pf2 = Pb[o]; pf3 = Pb[o + 1];
+          if (st < KS1 && lane < 16) {   // first half group: the packed slot
+            const int s1 = st, gs = lane >> 2, which = lane & 3;
+            const size_t os = main_len + ((size_t)s1 * 4 + gs) * 2 + (which & 1);
+            pfs = which < 2 ? Ib[os] : Pb[os];
+          }
+        }
+      };
+      auto produce = [&](int rr) {
+        const int st = rr * R + kp;
+        if (st >= nsteps) return;   // uniform per wave
+        const int s1 = st % KS1;
+        float4* sl = slots + ((rr & 1) * 8 + w) * kSlotF4;
+        float4 o0, o1;
+        fold_w(pf0, pf1, pf2, pf3, o0, o1);
+        if (s1 == 0) {   // uniform: lanes g = 0 hold the shared slot
+          float4 q0, q1;
+          fold_w_special(pf0, pf1, pf2, pf3, q0, q1);
+          if (g == 0) { o0 = q0; o1 = q1; }
+        }
+        sl[lane] = o0;
+        sl[64 + lane] = o1;
+        if (st < KS1) {   // uniform: first half group, the packed slot's second column
+          float4* sg = stage + w * 16;
+          if (lane < 16) sg[lane] = pfs;
+          if (p == 0) {
+            const float4 a0 = sg[4 * g], a1 = sg[4 * g + 1], b0 = sg[4 * g + 2], b1 = sg[4 * g + 3];
+            if (s1 == 0 && g == 0) fold_w_special(a0, a1, b0, b1, o0, o1);
+            else fold_w(a0, a1, b0, b1, o0, o1);
+            sl[128 + g] = o0;
+            sl[132 + g] = o1;
+          }
+        }
+      };
+
+      f4 d2[2][8];
+#pragma unroll
+      for (int s = 0; s < 2; ++s)
+#pragma unroll
+        for (int v = 0; v < 8; ++v) d2[s][v] = f4{0.f, 0.f, 0.f, 0.f};
+      f4 d1[2][4];
+#pragma unroll
+      for (int tt = 0; tt < 2; ++tt)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) d1[tt][b] = f4{0.f, 0.f, 0.f, 0.f};
+      float cre = 0.f, cim = 0.f;
+
+      // stage 2 of half group h (its stage-1 accumulators are complete)
+      auto stage2 = [&](int h) {
+        // even rows: + (-1)^p (W(N/4) + W(3N/4)) T(N/4) of each column
+        const float sg = (p & 1) ? -1.0f : 1.0f;
+#pragma unroll
+        for (int rr = 0; rr < 4; ++rr) {
+          const float xr = __shfl(cre, 4 * g + rr, 64), xi = __shfl(cim, 4 * g + rr, 64);
+          d1[0][0][rr] = fmaf(sg, xr, d1[0][0][rr]);
+          d1[1][0][rr] = fmaf(sg, xi, d1[1][0][rr]);
+        }
+        // accumulator rows 4g + r are (pair 2g + r/2, member r%2)
+#pragma unroll
+        for (int s = 0; s < 2; ++s) {
+          const f4 Ur = d1[0][2 * s], Ui = d1[1][2 * s], Vr = d1[0][2 * s + 1], Vi = d1[1][2 * s + 1];
+          float a0u = 0.f, a0v = 0.f;
+#pragma unroll
+          for (int h2 = 0; h2 < 2; ++h2) {
+            const int ra = 2 * h2, rb = 2 * h2 + 1;
+            float URp = Ur[ra] + Ur[rb], URm = Ur[ra] - Ur[rb], UIp = Ui[ra] + Ui[rb], UIm = Ui[ra] - Ui[rb];
+            float VRp = Vr[ra] + Vr[rb], VRm = Vr[ra] - Vr[rb], VIp = Vi[ra] + Vi[rb], VIm = Vi[ra] - Vi[rb];
+            if (h == 0 && h2 == 0) {   // uniform
+              if (g == 0) {            // pair 0: packed slot (member 0) and column nx/4 (member 1)
+                a0u = Ur[ra] + Ui[ra];
+                a0v = Vi[ra] - Vr[ra];
+                URm = Ur[ra] - Ui[ra];
+                VIm = Vi[ra] + Vr[ra];
+                URp = Ur[rb];
+                VIp = Vi[rb];
+                UIp = Ui[rb];
+                VRp = Vr[rb];
+                UIm = 0.f;
+                VRm = 0.f;
+              }
+            }
+            const float4 Af = F2s[(h * 2 + h2) * 64 + lane];
+            d2[s][0] = mma(Af.x, URp, d2[s][0]);
+            d2[s][1] = mma(Af.x, VIp, d2[s][1]);
+            d2[s][2] = mma(Af.y, UIm, d2[s][2]);
+            d2[s][3] = mma(Af.y, VRm, d2[s][3]);
+            d2[s][4] = mma(Af.z, URm, d2[s][4]);
+            d2[s][5] = mma(Af.z, VIm, d2[s][5]);
+            d2[s][6] = mma(Af.w, UIp, d2[s][6]);
+            d2[s][7] = mma(Af.w, VRp, d2[s][7]);
+          }
+          if (h == 0) {   // a(0) = Y(0) + Y(nx/2), weight 1 at every even dx
+            const float xu = __shfl(a0u, p, 64), xv = __shfl(a0v, p, 64);
+#pragma unroll
+            for (int rr = 0; rr < 4; ++rr) {
+              d2[s][0][rr] += xu;
+              d2[s][1][rr] += xv;
+            }
+          }
+        }
+#pragma unroll
+        for (int tt = 0; tt < 2; ++tt)
+#pragma unroll
+          for (int b = 0; b < 4; ++b) d1[tt][b] = f4{0.f, 0.f, 0.f, 0.f};
+        cre = 0.f;
+        cim = 0.f;
+      };
+
+      // one consumed K-step: sl is its LDS slot, tc / ts its CTF values; the
+      // next step's CTF values are loaded into tn / tsn
+      auto step = [&](int st, int h, int s1, const float4* sl, const float4& tc, const float4& tsc, float4& tn,
+                      float4& tsn) {
+        if (st + 1 < nsteps) {
+          tn = Tb[(size_t)(st + 1) * 64 + lane];
+          if (st + 1 < KS1) {   // uniform
+            if (p == 0) tsn = Tb[tmain + (size_t)(st + 1) * 4 + g];
+          }
+        }
+        const float4 x0 = sl[lane], x1 = sl[64 + lane], bf = F1s[s1 * 64 + lane];
+        Ops o;
+        if (s1 == 0) {   // uniform: lanes g = 0 hold the shared slot
+          float cr = 0.f, ci = 0.f;
+          const Ops a = ops_regular(x0, x1, tc), b = ops_special(x0, x1, tc, cr, ci);
+          const bool sp = g == 0;
+          o.u0r = sp ? b.u0r : a.u0r; o.u0i = sp ? b.u0i : a.u0i;
+          o.v0r = sp ? b.v0r : a.v0r; o.v0i = sp ? b.v0i : a.v0i;
+          o.u1r = sp ? b.u1r : a.u1r; o.u1i = sp ? b.u1i : a.u1i;
+          o.v1r = sp ? b.v1r : a.v1r; o.v1i = sp ? b.v1i : a.v1i;
+          cre = sp ? cr : 0.f;
+          cim = sp ? ci : 0.f;
+        } else {
+          o = ops_regular(x0, x1, tc);
+        }
+        if (__builtin_amdgcn_readfirstlane(h) == 0) {   // uniform
+          if (p == 0) {  // packed slot: + i x (the column nx/2)
+            const float4 y0 = sl[128 + g], y1 = sl[132 + g];
+            Ops m;
+            float cr = 0.f, ci = 0.f;
+            if (s1 == 0 && g == 0) m = ops_special(y0, y1, tsc, cr, ci);
+            else m = ops_regular(y0, y1, tsc);
+            o.u0r -= m.u0i; o.u0i += m.u0r;
+            o.v0r -= m.v0i; o.v0i += m.v0r;
+            o.u1r -= m.u1i; o.u1i += m.u1r;
+            o.v1r -= m.v1i; o.v1i += m.v1r;
+            cre -= ci; cim += cr;
+          }
+        }
+        d1[0][0] = mma(o.u0r, bf.x, d1[0][0]);
+        d1[1][0] = mma(o.u0i, bf.x, d1[1][0]);
+        d1[0][1] = mma(o.v0r, bf.y, d1[0][1]);
+        d1[1][1] = mma(o.v0i, bf.y, d1[1][1]);
+        d1[0][2] = mma(o.u1r, bf.z, d1[0][2]);
+        d1[1][2] = mma(o.u1i, bf.z, d1[1][2]);
+        d1[0][3] = mma(o.v1r, bf.w, d1[0][3]);
+        d1[1][3] = mma(o.v1i, bf.w, d1[1][3]);
+        if (s1 == KS1 - 1) stage2(h);   // uniform: half group h done
+      };
+
+      // CTF values of the consumed K-steps, one step ahead, in two register
+      // sets used alternately (steps are taken in pairs)
+      float4 ta = Tb[lane], tsa = make_float4(0.f, 0.f, 0.f, 0.f), tb = ta, tsb = tsa;
+      if (p == 0) tsa = Tb[tmain + g];
+
+      load(0);
+      produce(0);
+      if (nrounds > 1) load(1);
+      __syncthreads();
+      int h = 0, s1 = 0;   // half group and K-step of the next consumed step
+      for (int r = 0; r < nrounds; ++r) {
+        if (r + 1 < nrounds) produce(r + 1);
+        if (r + 2 < nrounds) load(r + 2);
+        const int st0 = r * R, st1 = min(st0 + R, nsteps);
+        const float4* sl = slots + ((r & 1) * 8 + gi * R) * kSlotF4;
+        int st = st0;
+        for (; st + 1 < st1; st += 2) {
+          step(st, h, s1, sl, ta, tsa, tb, tsb);
+          if (++s1 == KS1) { s1 = 0; ++h; }
+          step(st + 1, h, s1, sl + kSlotF4, tb, tsb, ta, tsa);
+          if (++s1 == KS1) { s1 = 0; ++h; }
+          sl += 2 * kSlotF4;
+        }
+        if (st < st1) {   // odd step count: the values move back to set a
+          step(st, h, s1, sl, ta, tsa, tb, tsb);
+          if (++s1 == KS1) { s1 = 0; ++h; }
+          ta = tb;
+          tsa = tsb;
+        }
+        __syncthreads();
+      }
+
+      // epilogue of this wave's evaluation (image ic, orientation qc, CTF c)
+      const double A = ma.istats[3 * ic + 2];
+      const double Bq = ma.B[(size_t)qc * ma.nc + cc];
+      bioem_erec* out = ma.rec + ((size_t)ic * nslots + sc) * ma.nc + cc;
+      if (!(A > 0.0) || !(Bq > 0.0)) {   // uniform: degenerate image or projection
+        if (mine && lane == 0) *out = bioem_erec{-1.0f, 0.0f, -1, 0};
+        continue;
+      }
+      // X at (+-k, +-dx) from the eight stage-2 products, squared in place
+      // (-1 marks slots outside the window and the duplicates of k = 0, dx = 0)
+      float x2max = 0.0f;
+#pragma unroll
+      for (int s = 0; s < 2; ++s) {
+        const int kk = 2 * p + s;
+        const bool kpos = kk <= S, kneg = kpos && kk > 0;
+#pragma unroll
+        for (int rr = 0; rr < 4; ++rr) {
+          const int rho = 4 * g + rr;
+          const bool ap = 2 * rho <= S, am = ap && rho > 0, bp = 2 * rho + 1 <= S;
+          const float Eap = d2[s][0][rr] - d2[s][1][rr], Eam = d2[s][0][rr] + d2[s][1][rr];
+          const float Oap = d2[s][2][rr] + d2[s][3][rr], Oam = d2[s][2][rr] - d2[s][3][rr];
+          const float Ebp = d2[s][4][rr] - d2[s][5][rr], Ebm = d2[s][4][rr] + d2[s][5][rr];
+          const float Obp = d2[s][6][rr] + d2[s][7][rr], Obm = d2[s][6][rr] - d2[s][7][rr];
+          float x[8];
+          x[0] = Eap - Oap; x[1] = Eap + Oap; x[2] = Eam - Oam; x[3] = Eam + Oam;
+          x[4] = Ebp - Obp; x[5] = Ebp + Obp; x[6] = Ebm - Obm; x[7] = Ebm + Obm;
+          const bool ok[8] = {kpos && ap, kpos && am, kneg && ap, kneg && am,
+                              kpos && bp, kpos && bp, kneg && bp, kneg && bp};
+#pragma unroll
+          for (int v = 0; v < 8; ++v) {
+            const float x2 = ok[v] ? x[v] * x[v] : -1.0f;
+            d2[s][v][rr] = x2;
+            x2max = fmaxf(x2max, x2);
+          }
+        }
+      }
+      const float wmax = wmax_f(x2max);
+      const int esc = 2 * (ma.iexpo[ic] + ma.pexpo[qc]);
+      const double kappa = ldexp(ma.kscale / (A * Bq), esc);
+      const double rho2 = fmin((double)wmax * kappa, 1.0 - 0x1p-52);
+      const float cu = (float)(kappa / (1.0 - rho2));
+      const float base = wmax * cu;
+      const double n = (double)ma.nx * ma.ny;
+      const float c2 = (float)(0.5 * n - 1.0);
+      float sum = 0.0f;
+      if (c2 >= 1024.0f) {
+        // log1p(u) by its degree-3 series on [0, 0.05]; a term with u >= 0.05
+        // is below e^-51 of the maximum term (1) and is left out, and a slot
+        // whose term is left out in every lane costs no exponential
+        const float c2l2e = c2 * 1.4426950408889634f;
+        const float p1 = -c2l2e, p2 = 0.5f * c2l2e, p3 = -c2l2e / 3.0f;
+#pragma unroll
+        for (int s = 0; s < 2; ++s)
+#pragma unroll
+          for (int v = 0; v < 8; ++v)
+#pragma unroll
+            for (int rr = 0; rr < 4; ++rr) {
+              const float x2 = d2[s][v][rr];
+              const float u = fmaf(-x2, cu, base);
+              const bool take = x2 >= 0.0f && u < 0.05f;
+              if (__builtin_amdgcn_ballot_w64(take)) {
+                const float uc = fmaxf(u, 0.0f);
+                const float tm = __builtin_amdgcn_exp2f(uc * (p1 + uc * (p2 + uc * p3)));
+                sum += take ? tm : 0.0f;
+              }
+            }
+      } else {
+#pragma unroll
+        for (int s = 0; s < 2; ++s)
+#pragma unroll
+          for (int v = 0; v < 8; ++v)
+#pragma unroll
+            for (int rr = 0; rr < 4; ++rr) {
+              const float x2 = d2[s][v][rr];
+              const float u = fmaxf(fmaf(-x2, cu, base), 0.0f);
+              const float tm = __expf(-c2 * log1p_f(u));
+              sum += x2 >= 0.0f ? tm : 0.0f;
+            }
+      }
+      const float tot = wsum_f(sum);
+      if (mine && lane == 0) *out = bioem_erec{wmax, tot, -1, 0};
+    }
+  }
 }
 
-constexpr int kMfWaves = 8;
-constexpr int kMfTileImages = 32;
-constexpr int kMfTileSlots = 128;
+constexpr int kMfTileImages = 8;
+constexpr int kMfTileSlots = 64;
 
 int mf_device_cus() {
   int dev = 0, ncu = 256;
@@ -512,10 +702,11 @@ int mf_device_cus() {
 }  // namespace
 
 size_t mf_len(int nx, int ny) { return mf_item_len(mf_geom(nx, ny)); }
+size_t mf_table_len(int nx, int ny) { return mf_tab_len(mf_geom(nx, ny)); }
 
 size_t mf32_smem_bytes(int nx, int ny) {
   const MfGeom G = mf_geom(nx, ny);
-  return sizeof(float4) * ((size_t)G.KS1 * 64 + (size_t)G.nHG * 128);
+  return sizeof(float4) * ((size_t)G.KS1 * 64 + (size_t)G.nHG * 128 + 2 * 8 * kSlotF4 + kMfWaves * 16);
 }
 
 bool mf32_supported(int nx, int ny, int S) {
@@ -523,20 +714,20 @@ bool mf32_supported(int nx, int ny, int S) {
          mf32_smem_bytes(nx, ny) <= kMaxSmem;
 }
 
-hipError_t launch_mf_copy_spec(hipStream_t s, const float2* spec, int n, int nx, int ny, float4* out) {
+hipError_t launch_mf_copy_spec(hipStream_t s, const float2* spec, int n, int nx, int ny, bool zero_dc,
+                               float4* out) {
   const long total = (long)n * (long)mf_len(nx, ny);
   if (total == 0) return hipSuccess;
   hipLaunchKernelGGL(k_mf_copy_spec, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, spec, total, nx, ny,
-                     out);
+                     zero_dc ? 1 : 0, out);
   return hipGetLastError();
 }
 
-hipError_t launch_mf_copy_at(hipStream_t s, const float2* ispec, const float* table, int ni, int nc, int nx, int ny,
-                             float4* out) {
-  const long total = (long)ni * nc * (long)mf_len(nx, ny);
+hipError_t launch_mf_copy_table(hipStream_t s, const float* table, int nc, int nx, int ny, float4* out) {
+  const long total = (long)nc * (long)mf_table_len(nx, ny);
   if (total == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_mf_copy_at, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, ispec, table, total,
-                     nc, nx, ny, out);
+  hipLaunchKernelGGL(k_mf_copy_table, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, table, total, nx,
+                     ny, out);
   return hipGetLastError();
 }
 
@@ -552,34 +743,45 @@ hipError_t launch_mf_tables(hipStream_t s, int nx, int ny, int S, float4* tabs) 
   return hipGetLastError();
 }
 
-hipError_t launch_logpost_mf32(hipStream_t s, const LogpostArgs& a, const float4* at, const float4* pm,
-                               const float4* tabs, int ti, int ts) {
+hipError_t launch_logpost_mf32(hipStream_t s, const LogpostArgs& a, const float4* im, const float4* pm,
+                               const float4* tm, const float4* tabs, int ti, int ts) {
   const MfGeom G = mf_geom(a.nx, a.ny);
   MfArgs ma{};
-  ma.a = a;
-  ma.at = at;
-  ma.pm = pm;
+  ma.im = im; ma.pm = pm; ma.tm = tm;
   ma.F1 = tabs;
   ma.F2 = tabs + G.KS1 * 64;
+  ma.istats = a.istats; ma.iexpo = a.iexpo; ma.pexpo = a.pexpo; ma.B = a.B;
+  ma.cand = a.cand; ma.k = a.k;
+  ma.rec = a.rec;
+  ma.kscale = a.kscale;
+  ma.len = (long)mf_item_len(G);
+  ma.tlen = (long)mf_tab_len(G);
+  ma.ni = a.ni; ma.nq = a.nq; ma.nc = a.nc; ma.nx = a.nx; ma.ny = a.ny; ma.S = a.S;
   ma.KS1 = G.KS1;
   ma.nHG = G.nHG;
-  ma.len = (long)mf_len(a.nx, a.ny);
+  // waves per pair: the CTF sets of one pair share its products (a power of
+  // two up to 8, so a group of pairs fills the workgroup)
+  int wpp = 1;
+  while (wpp < a.nc && wpp < kMfWaves) wpp *= 2;
+  ma.wpp = wpp;
+  ma.G = kMfWaves / wpp;
+  ma.R = kMfWaves / ma.G;            // every wave makes one K-step per round
+  ma.passes = (a.nc + wpp - 1) / wpp;
   const int nslots = a.cand ? a.k : a.nq;
   ma.ti = ti > 0 ? ti : kMfTileImages;
   ma.ts = ts > 0 ? ts : kMfTileSlots;
   ma.n_ti = (a.ni + ma.ti - 1) / ma.ti;
   ma.n_ts = (nslots + ma.ts - 1) / ma.ts;
-  const long n_items = (long)ma.n_ti * ma.n_ts * ma.ti * ma.ts * a.nc;
-  if (n_items <= 0) return hipSuccess;
-  if (n_items > 0x7fffffffL) return hipErrorInvalidValue;
+  const long groups = (long)ma.n_ti * ma.n_ts * (((long)ma.ti * ma.ts + ma.G - 1) / ma.G) * ma.passes;
+  if (groups <= 0) return hipSuccess;
+  if ((long)ma.n_ti * ma.n_ts > 0x7fffffffL || (long)ma.ti * ma.ts * ma.passes > 0x7fffffffL)
+    return hipErrorInvalidValue;
   const size_t smem = mf32_smem_bytes(a.nx, a.ny);
-  auto kern = k_logpost_mf32<kMfWaves>;
-  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
+  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_logpost_mf32),
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
   if (e != hipSuccess) return e;
-  const long want = (n_items + kMfWaves - 1) / kMfWaves;
-  const int grid = (int)std::min<long>(want, (long)mf_device_cus());
-  hipLaunchKernelGGL(kern, dim3(grid), dim3(64 * kMfWaves), smem, s, ma);
+  const int grid = (int)std::min<long>(groups, (long)mf_device_cus());
+  hipLaunchKernelGGL(k_logpost_mf32, dim3(grid), dim3(64 * kMfWaves), smem, s, ma);
   return hipGetLastError();
 }
 
