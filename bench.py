@@ -43,8 +43,57 @@ def alg_flops(n: int, S: int):
 
 
 ALG_FP32_PER_EVAL, ALG_FP64_PER_EVAL = alg_flops(224, 20)
+# MI355X dense peaks (TFLOP/s): FP32 matrix cores (the FP32 vector ALUs reach
+# the same figure only with packed instructions, which this build does not
+# use), FP64, and fp16/bf16 matrix cores.
 PEAK_FP32_TFLOPS = 157.3
 PEAK_FP64_TFLOPS = 78.6
+PEAK_F16_MFMA_TFLOPS = 2500.0
+GOLDEN = os.path.join(ROOT, "tests", "golden", "config2_full_grid.json")
+
+
+def issued_mfma_flops(prec: str, n: int, S: int) -> float:
+    """Matrix-core flops the kernel issues per evaluation (box n x n, window S).
+
+    f32: per half group of 16 column pairs, one 16x16x4 FP32 product per
+    stage-1 K-step and block (4 blocks, re and im) and 32 stage-2 products.
+    split: per 16-column tile, 2 x 3 16x16x32 products per 32-row K-step and
+    window tile plus 3 per pair of window tiles in stage 2."""
+    if prec == "f32":
+        H = n // 2
+        j1 = n // 4 - 1 if n % 4 == 0 else (n - 2) // 4
+        ks1 = (j1 + 1 + 3) // 4
+        nreg = H // 2 - 1 if n % 4 == 0 else (H - 1) // 2
+        nhg = (1 + nreg + 7) // 8
+        return float((8 * ks1 + 32) * nhg * 2 * 16 * 16 * 4)
+    nt = (S + 8) // 8
+    ks = (n + 31) // 32
+    mt = (n // 2 + 15) // 16
+    return float(mt * (ks * nt * 2 * 3 + nt * nt * 3) * 2 * 16 * 16 * 32)
+
+
+def roofline_of(prec: str, evals: float, t_launch: float, f32: float, f64: float, kernel: str, n: int, S: int,
+                traffic=None) -> dict:
+    """Roofline record of one posterior launch: the algorithmic work (the
+    pruned transform and pointwise product at the peak of the unit that does
+    the contraction, the likelihood epilogue at the FP64 peak) against the
+    launch's measured duration.  frac = time at the roof / measured time;
+    achieved = frac x peak."""
+    peak = PEAK_FP32_TFLOPS if prec == "f32" else PEAK_F16_MFMA_TFLOPS
+    roof_t = f32 / (peak * 1e12) + f64 / (PEAK_FP64_TFLOPS * 1e12)
+    frac = evals * roof_t / t_launch
+    issued = issued_mfma_flops(prec, n, S)
+    return {"bound": "mfma", "achieved": round(frac * peak, 3), "peak": peak, "unit": "TFLOP/s",
+            "frac": round(frac, 4), "traffic": traffic,
+            "traffic_unit": "bytes per launch (FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0)",
+            "kernel": kernel, "kernel_ms_per_launch": round(t_launch * 1e3, 3), "evals_per_launch": evals,
+            "roof_evals_per_s": round(1.0 / roof_t, 1),
+            "alg_mflop_per_eval": {"transform_fp32": round(f32 / 1e6, 4), "epilogue_fp64": round(f64 / 1e6, 4)},
+            "issued_mfma_mflop_per_eval": round(issued / 1e6, 4),
+            "issued_over_algorithmic": round(issued / f32, 3),
+            "peak_note": ("FP32 matrix cores (157.3 TF) for the transform, FP64 (78.6 TF) for the epilogue"
+                          if prec == "f32" else
+                          "fp16/bf16 matrix cores (2.5 PF dense) for the transform, FP64 (78.6 TF) for the epilogue")}
 
 
 def source_hash() -> str:
@@ -63,11 +112,9 @@ def recorded_traffic(kernel: str, prec: str, evals_per_launch: float):
 
     The summaries under profiles/ carry one 'bench-traffic:' record per
     measured configuration; a record counts only if it was taken on the
-    current sources, the same kernel, precision and launch size, and the
-    default launch shape (no BIOEM_SPLIT_SHAPE override)."""
+    current sources, the same kernel, precision and launch size (default
+    launch shape)."""
     import glob
-    if os.environ.get("BIOEM_SPLIT_SHAPE"):
-        return None
     want = source_hash()
     for f in sorted(glob.glob(os.path.join(ROOT, "profiles", "*.md"))):
         with open(f) as fh:
@@ -124,7 +171,7 @@ def main() -> int:
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--prec", default="split_f16", choices=["f32", "split_f16", "split_bf16"])
+    ap.add_argument("--prec", default="f32", choices=["f32", "split_f16", "split_bf16"])
     ap.add_argument("--images", type=int, default=1000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", default="2x8x2")
@@ -194,10 +241,22 @@ def main() -> int:
     evals = ni * nq * nc
     log(f"inputs ready: {ni} images, {nq} orientations x {nc} CTF sets, S={S}")
 
+    calls = {"project": 0.0, "prepare_images": 0.0, "logpost": 0.0}
+
     def step():
+        t0 = time.perf_counter()
         proj = P.project(ctx, model, quats, cls.nx, cls.ny, cls.pixel_A)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
         im = P.prepare_images(ctx, images)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
         out = P.logpost(ctx, proj, im, ctf, S, prec=args.prec, device_out=True)
+        torch.cuda.synchronize()
+        t3 = time.perf_counter()
+        calls["project"] += t1 - t0
+        calls["prepare_images"] += t2 - t1
+        calls["logpost"] += t3 - t2
         proj.free()
         im.free()
         return out
@@ -207,6 +266,8 @@ def main() -> int:
         torch.cuda.synchronize()
         log(f"warmup {w + 1}/{args.warmup} done")
     ctx.set_timing(True)
+    for key in calls:
+        calls[key] = 0.0
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for k in range(args.steps):
@@ -224,30 +285,38 @@ def main() -> int:
     # ---- roofline of the main kernel ------------------------------------------
     per_launch_evals = kevals / max(launches, 1)
     t_launch = kms / max(launches, 1) * 1e-3
-    fp32_equiv = per_launch_evals * (ALG_FP32_PER_EVAL + 2.0 * ALG_FP64_PER_EVAL)
-    achieved = fp32_equiv / t_launch / 1e12
-    kname = "k_logpost_f32" if args.prec == "f32" else "k_logpost_split"
-    roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP32_TFLOPS,
-                "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_TFLOPS, 4),
-                "traffic": recorded_traffic(kname, args.prec, per_launch_evals),
-                "traffic_unit": "bytes per launch (FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0)",
-                "kernel": kname,
-                "kernel_ms_per_launch": round(t_launch * 1e3, 3), "launches": launches,
-                "evals_per_launch": per_launch_evals}
+    kname = "k_logpost_mf32" if args.prec == "f32" else "k_logpost_split"
+    roofline = roofline_of(args.prec, per_launch_evals, t_launch, ALG_FP32_PER_EVAL, ALG_FP64_PER_EVAL, kname,
+                           cls.nx, S, recorded_traffic(kname, args.prec, per_launch_evals))
+    roofline["launches"] = launches
+
+    # ---- accuracy of the timed run: its first images against the stored
+    # FP64 oracle values of the same images (tests/golden) ----------------------
+    dlogp = None
+    if os.path.exists(GOLDEN):
+        with open(GOLDEN) as f:
+            gold = json.load(f)
+        ng = min(len(gold["images"]), ni)
+        ref = np.array([r["logp"] for r in gold["images"][:ng]])
+        d = np.abs(logp[:ng] - ref)
+        dlogp = {"images": ng, "max": float(d.max()), "median": float(np.median(d)),
+                 "against": "tests/golden/config2_full_grid.json (FP64 oracle, full grid)"}
 
     line = {"metric": METRIC, "value": value, "unit": "evals/s", "n_gpus": 1, "steps": args.steps,
             "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True,
             "scaling": "weak", "vs_baseline": None,
-            "dtype": {"f32": "f32 transform, f64 likelihood",
-                      "split_f16": "f16x2 split on MFMA (f32 acc), f64 likelihood",
-                      "split_bf16": "bf16x2 split on MFMA (f32 acc), f64 likelihood"}[args.prec],
+            "dtype": {"f32": "f32 (FP32 matrix cores, FP32 accumulation), f64 likelihood terms",
+                      "split_f16": "f16x2 split on MFMA (f32 acc), f64 likelihood terms",
+                      "split_bf16": "bf16x2 split on MFMA (f32 acc), f64 likelihood terms"}[args.prec],
             "data": "synthetic",
             "config": {"workload": "224x224 px at 1.32 A/px, 1500-sphere model, "
                                    f"{ni} images x {nq} orientations x {nc} CTF sets, shifts +-{S}",
                        "images": ni, "orientations": nq, "ctf_sets": nc, "box": cls.nx,
                        "max_shift": S, "evals_per_step": evals, "prec": args.prec,
                        "step": "bioem_project + bioem_prepare_images + bioem_logpost"},
-            "roofline": roofline}
+            "roofline": roofline,
+            "dlogp_vs_fp64": dlogp,
+            "ms_per_call": {k: round(v / args.steps * 1e3, 3) for k, v in calls.items()}}
     if not args.no_cpu_baseline:
         log(f"timing the CPU oracle on a {args.cpu_sample} sample")
         line["cpu_baseline"] = cpu_baseline(args.cpu_sample)
@@ -333,7 +402,6 @@ def run_mixed(args, P, ctx, torch, dev) -> int:
     models = [torch.from_numpy(m).to(dev) for m in wl.models]
     classes = []
     evals = 0
-    fp_equiv = 0.0
     for cls in wl.classes:
         imgs = torch.empty((per, cls.ny, cls.nx), dtype=torch.float32, device=dev)
         for m in range(2):
@@ -352,8 +420,6 @@ def run_mixed(args, P, ctx, torch, dev) -> int:
                             ctf=torch.from_numpy(cls.ctf).to(dev)))
         e = 2 * per * len(cls.quats) * len(cls.ctf)
         evals += e
-        f32, f64 = alg_flops(cls.nx, cls.max_shift)
-        fp_equiv += e * (f32 + 2.0 * f64)
     torch.cuda.synchronize()
     log(f"inputs ready: {evals} evaluations per step")
 
@@ -394,7 +460,18 @@ def run_mixed(args, P, ctx, torch, dev) -> int:
         res[mode] = dict(dt=dt, kms=kms / args.steps, launches=launches // args.steps)
         log(f"{mode}: {evals / dt:.4g} evals/s, kernel {kms / args.steps:.1f} ms per step")
     p, q = res["persistent"], res["per_job"]
-    achieved = fp_equiv / (p["kms"] * 1e-3) / 1e12
+    # the work of every class at its own box and window, against the launch
+    # (or launches) of one step
+    peak = PEAK_FP32_TFLOPS if args.prec == "f32" else PEAK_F16_MFMA_TFLOPS
+    roof_t = 0.0
+    for c in classes:
+        f32c, f64c = alg_flops(c["cls"].nx, c["cls"].max_shift)
+        roof_t += 2 * per * len(c["cls"].quats) * len(c["cls"].ctf) * (
+            f32c / (peak * 1e12) + f64c / (PEAK_FP64_TFLOPS * 1e12))
+    frac = roof_t / (p["kms"] * 1e-3)
+    mixed_roof = {"bound": "mfma", "achieved": round(frac * peak, 3), "peak": peak, "unit": "TFLOP/s",
+                  "frac": round(frac, 4), "traffic": None, "kernel": "k_logpost_batch",
+                  "kernel_ms_per_launch": round(p["kms"] / max(p["launches"], 1), 3), "launches": p["launches"]}
     # ensemble posterior, Eq. (pb2), of the two models over every image (each
     # class holds images of both): its log posterior on a grid of weights,
     # whose maximum estimates the mixing fraction, and how often the
@@ -431,11 +508,7 @@ def run_mixed(args, P, ctx, torch, dev) -> int:
                                    "(4608,16), shifts 8/11/16/20, one persistent launch",
                        "evals_per_step": evals, "prec": args.prec, "autotune": not args.no_autotune,
                        "step": "bioem_project + bioem_prepare_images + bioem_logpost_batch"},
-            "roofline": {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP32_TFLOPS,
-                         "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_TFLOPS, 4),
-                         "traffic": None, "kernel": "k_logpost_batch",
-                         "kernel_ms_per_launch": round(p["kms"] / max(p["launches"], 1), 3),
-                         "launches": p["launches"]},
+            "roofline": mixed_roof,
             "per_job": {"value": evals / q["dt"], "ms_per_step": q["dt"] * 1e3,
                         "kernel_ms_per_step": q["kms"], "launches_per_step": q["launches"]},
             "persistent_over_per_job": q["dt"] / p["dt"],

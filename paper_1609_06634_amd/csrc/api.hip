@@ -1,5 +1,6 @@
 // Host side of the C ABI: argument validation, device memory, chunking and
 // launch order.  All device work goes to the context's stream.
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -120,6 +121,15 @@ bioem_status plan_job(bioem_ctx* ctx, const bioem_job& jb, int prec, int out_mem
     for (size_t e = 0; e < hcand.size(); ++e)
       if (hcand[e] < 0 || hcand[e] >= nq)
         return fail(ctx, BIOEM_EINVAL, "%s: candidate %zu = %d outside [0, %d)", who, e, hcand[e], nq);
+    // a repeated orientation would be scored and summed twice
+    std::vector<int32_t> row(jb.k);
+    for (int i = 0; i < ni; ++i) {
+      std::copy(hcand.begin() + (size_t)i * jb.k, hcand.begin() + (size_t)(i + 1) * jb.k, row.begin());
+      std::sort(row.begin(), row.end());
+      if (std::adjacent_find(row.begin(), row.end()) != row.end())
+        return fail(ctx, BIOEM_EINVAL, "%s: image %d lists orientation %d twice among its candidates", who, i,
+                    *std::adjacent_find(row.begin(), row.end()));
+    }
   }
   J.proj = proj; J.imgs = imgs;
   J.nx = nx; J.ny = ny; J.nq = nq; J.ni = ni; J.nc = nc; J.S = S;
@@ -580,6 +590,22 @@ bioem_status bioem_prepare_images(bioem_ctx* ctx, const float* imgs, int32_t ni,
   hipStream_t s = ctx->stream;
   const int mh = nx / 2 + 1;
   const size_t len = (size_t)mh * ny, slen = (size_t)mh * spec_ld(ny), npix = (size_t)nx * ny;
+  // every pixel must be finite (checked before any work is enqueued)
+  if (in_mem == BIOEM_MEM_HOST) {
+    for (size_t e = 0; e < npix * ni; ++e)
+      if (!std::isfinite(imgs[e]))
+        return fail(ctx, BIOEM_EINVAL, "bioem_prepare_images: pixel %zu of image %zu is not finite", e % npix,
+                    e / npix);
+  } else {
+    DevMem flag;
+    unsigned hflag = 0;
+    HIP_OR_FAIL(ctx, flag.alloc(sizeof(unsigned)));
+    HIP_OR_FAIL(ctx, hipMemsetAsync(flag.p, 0, sizeof(unsigned), s));
+    HIP_OR_FAIL(ctx, launch_flag_nonfinite(s, imgs, npix * ni, flag.as<unsigned>()));
+    HIP_OR_FAIL(ctx, hipMemcpyAsync(&hflag, flag.p, sizeof(unsigned), hipMemcpyDeviceToHost, s));
+    HIP_OR_FAIL(ctx, hipStreamSynchronize(s));
+    if (hflag) return fail(ctx, BIOEM_EINVAL, "bioem_prepare_images: an image holds a non-finite pixel");
+  }
   bioem_imgs* p = new (std::nothrow) bioem_imgs;
   if (!p) return fail(ctx, BIOEM_ENOMEM, "bioem_prepare_images: host allocation");
   p->n = ni; p->nx = nx; p->ny = ny; p->device = ctx->device;

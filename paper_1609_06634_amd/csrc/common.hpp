@@ -84,6 +84,8 @@ hipError_t launch_rdft2(hipStream_t s, const double* real_in, const float* real_
 hipError_t launch_spec_store(hipStream_t s, const double2* spec64, int n, int nx, int ny,
                              float2* spec, int32_t* expo);
 hipError_t launch_image_stats(hipStream_t s, const float* imgs, int n, int npix, double* stats);
+// *flag |= 1 if any of x[0..n) is NaN or infinite (flag zeroed by the caller).
+hipError_t launch_flag_nonfinite(hipStream_t s, const float* x, size_t n, unsigned* flag);
 // z-y-z Euler angles [n][3] (radians) -> unit quaternions [n][4] (w, x, y, z).
 hipError_t launch_euler_quat(hipStream_t s, const double* euler, int n, double* quats);
 // Fragment-order copies: complex spectra [n][nx/2+1][spec_ld(ny)] -> [n][tile_spec_len],

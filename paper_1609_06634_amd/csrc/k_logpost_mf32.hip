@@ -649,10 +649,13 @@ __global__ __launch_bounds__(64 * kMfWaves) void k_logpost_mf32(MfArgs ma) {
       float sum = 0.0f;
       if (c2 >= 1024.0f) {
         // log1p(u) by its degree-3 series on [0, 0.05]; a term with u >= 0.05
-        // is below e^-51 of the maximum term (1) and is left out, and a slot
-        // whose term is left out in every lane costs no exponential
+        // is below e^-51 of the maximum term (1) and is left out: only values
+        // with X^2 > wmax - 0.05/cu take part (marked slots hold -1, below the
+        // threshold kept at or above -0.5), and a slot left out in every lane
+        // costs no exponential
         const float c2l2e = c2 * 1.4426950408889634f;
         const float p1 = -c2l2e, p2 = 0.5f * c2l2e, p3 = -c2l2e / 3.0f;
+        const float thr = fmaxf((base - 0.05f) / cu, -0.5f);
 #pragma unroll
         for (int s = 0; s < 2; ++s)
 #pragma unroll
@@ -660,11 +663,10 @@ __global__ __launch_bounds__(64 * kMfWaves) void k_logpost_mf32(MfArgs ma) {
 #pragma unroll
             for (int rr = 0; rr < 4; ++rr) {
               const float x2 = d2[s][v][rr];
-              const float u = fmaf(-x2, cu, base);
-              const bool take = x2 >= 0.0f && u < 0.05f;
+              const bool take = x2 > thr;
               if (__builtin_amdgcn_ballot_w64(take)) {
-                const float uc = fmaxf(u, 0.0f);
-                const float tm = __builtin_amdgcn_exp2f(uc * (p1 + uc * (p2 + uc * p3)));
+                const float u = fminf(fmaxf(fmaf(-x2, cu, base), 0.0f), 0.05f);
+                const float tm = __builtin_amdgcn_exp2f(u * (p1 + u * (p2 + u * p3)));
                 sum += take ? tm : 0.0f;
               }
             }

@@ -398,8 +398,9 @@ __device__ __forceinline__ void split_item(const SplitArgs& sa, const uint4* __r
           for (int k = 0; k < NT * NT * 4; ++k) {
             const float x2 = acc2[e][k / (4 * NT)][(k / 4) % NT][k % 4];
             const float u = __builtin_amdgcn_fmed3f(fmaf(-x2, cu, base), 0.0f, 0.05f);
-            // slots outside the window have u clamped to 0.05: below e^-50
-            sum += __builtin_amdgcn_exp2f(u * (p1 + u * (p2 + u * p3)));
+            // slots outside the window are marked x2 = -1 and left out
+            const float t = __builtin_amdgcn_exp2f(u * (p1 + u * (p2 + u * p3)));
+            sum += x2 >= 0.0f ? t : 0.0f;
           }
         } else {
 #pragma unroll

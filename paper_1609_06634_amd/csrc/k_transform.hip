@@ -527,6 +527,22 @@ hipError_t launch_spec_store(hipStream_t s, const double2* spec64, int n, int nx
   return last();
 }
 
+// Sets *flag to 1 if any of the n values is not finite (NaN or infinite).
+__global__ __launch_bounds__(256) void k_flag_nonfinite(const float* __restrict__ x, size_t n,
+                                                        unsigned* __restrict__ flag) {
+  bool bad = false;
+  for (size_t e = (size_t)blockIdx.x * 256 + threadIdx.x; e < n; e += (size_t)gridDim.x * 256)
+    bad |= !isfinite(x[e]);
+  if (__any(bad) && (threadIdx.x & 63) == 0) atomicOr(flag, 1u);
+}
+
+hipError_t launch_flag_nonfinite(hipStream_t s, const float* x, size_t n, unsigned* flag) {
+  const unsigned blocks = (unsigned)std::min<size_t>((n + 255) / 256, 4096);
+  if (blocks == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_flag_nonfinite, dim3(blocks), dim3(256), 0, s, x, n, flag);
+  return last();
+}
+
 hipError_t launch_image_stats(hipStream_t s, const float* imgs, int n, int npix, double* stats) {
   hipLaunchKernelGGL(k_image_stats, dim3(n), dim3(256), 0, s, imgs, npix, stats);
   return last();

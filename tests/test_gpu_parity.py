@@ -183,3 +183,85 @@ def test_invalid_arguments(P, ctx, cfg1):
     im2 = P.prepare_images(ctx, np.zeros((1, 32, 32), np.float32))
     with pytest.raises(P.BioemError):
         P.logpost(ctx, proj, im2, cls.ctf, 2)             # box mismatch
+
+
+def test_nonfinite_pixels_rejected(P, ctx, cfg1):
+    """A NaN or infinite pixel is an invalid argument, found before any work
+    (host and device images)."""
+    import torch
+    _, _, imgs = cfg1
+    for bad in (np.nan, np.inf):
+        x = imgs[:3].copy()
+        x[1, 7, 9] = bad
+        with pytest.raises(P.BioemError) as e:
+            P.prepare_images(ctx, x)
+        assert e.value.status == -1
+        with pytest.raises(P.BioemError) as e:
+            P.prepare_images(ctx, torch.from_numpy(x).cuda())
+        assert e.value.status == -1
+    P.prepare_images(ctx, torch.from_numpy(imgs[:3].copy()).cuda()).free()
+
+
+def test_duplicate_candidates_rejected(P, ctx, cfg1):
+    wl, cls, imgs = cfg1
+    proj = P.project(ctx, wl.models[0], cls.quats[:10], cls.nx, cls.ny, cls.pixel_A)
+    im = P.prepare_images(ctx, imgs[:2])
+    cand = np.array([[1, 4, 7], [2, 5, 2]], np.int32)
+    with pytest.raises(P.BioemError) as e:
+        P.logpost(ctx, proj, im, cls.ctf, 2, cand_q=cand)
+    assert e.value.status == -1
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_zero_projections_degenerate(P, ctx, cfg1, prec):
+    """A model of zero weight projects to zero everywhere (every B = 0): each
+    image is degenerate, status 1 and log P = NaN, and the call succeeds."""
+    wl, cls, imgs = cfg1
+    model = wl.models[0].copy()
+    model[:, 4] = 0.0
+    proj = P.project(ctx, model, cls.quats[:5], cls.nx, cls.ny, cls.pixel_A)
+    out = P.logpost(ctx, proj, P.prepare_images(ctx, imgs[:3]), cls.ctf, 2, **KW[prec])
+    assert np.all(out["best"]["status"] == 1)
+    assert np.all(np.isnan(out["logp"]))
+
+
+# Relative accuracy of the window correlation X for each transform form
+# (a few units of the operand rounding: FP32 and the fp16 hi/lo split keep
+# about 22-24 bits, the bf16 split about 16).
+XREL = {"f32": 64 * 2.0 ** -24, "f32_valu": 64 * 2.0 ** -24, "split_f16": 16 * 2.0 ** -22,
+        "split_bf16": 16 * 2.0 ** -16}
+
+
+@pytest.mark.parametrize("prec", PRECS)
+@pytest.mark.parametrize("snr", [10.0, 100.0])
+def test_high_snr_logp(P, ctx, prec, snr):
+    """log P where rho^2 approaches 1.  An error dX/X in the correlation moves
+    l by about (n-2) rho^2/(1-rho^2) dX/X, so the bar widens as the fit
+    tightens: each image is held to max(bar, that bound at its own maximal
+    rho^2, from the oracle)."""
+    wl = make_workload(1, n_images=4)
+    cls = wl.classes[0]
+    rng = np.random.default_rng(int(snr))
+    imgs = np.array([O.render_image(wl.models[0], cls.img_quat[i], cls.img_ctf[i], cls.img_shift[i], cls.nx, cls.ny,
+                                    cls.pixel_A, 1.0, 0.0, rng.standard_normal((cls.ny, cls.nx)), snr)
+                     for i in range(4)], dtype=np.float32)
+    quats = cls.quats[:20]
+    r = O.logpost_oracle(imgs.astype(np.float64), wl.models[0], quats, cls.ctf, cls.pixel_A, cls.max_shift,
+                         method="fft")
+    proj = P.project(ctx, wl.models[0], quats, cls.nx, cls.ny, cls.pixel_A)
+    out = P.logpost(ctx, proj, P.prepare_images(ctx, imgs), cls.ctf, cls.max_shift, **KW[prec])
+    n = cls.nx * cls.ny
+    for i in range(4):
+        A = O.image_moments(imgs[i].astype(np.float64))[2]
+        # rho^2 at the maximum from the oracle's maximal log-likelihood
+        h = 0.5 * n
+        const = (math.lgamma(h - 1.0) - math.log(2.0) - 0.5 * math.log(n) + (1.0 - h) * math.log(math.pi * A))
+        q, c = int(r.best_q[i]), int(r.best_c[i])
+        i1 = O.filtered_projection(O.project_model(wl.models[0], quats[q], cls.nx, cls.ny, cls.pixel_A),
+                                   O.ctf_envelope_table(*cls.ctf[c], cls.nx, cls.ny, cls.pixel_A))
+        B = O.projection_norm(i1)
+        rho2 = -math.expm1((r.best_logl[i] - const + 0.5 * math.log(B)) / (1.0 - h))
+        tol = max(TOL[prec], (n - 2) * rho2 / (1.0 - rho2) * XREL[prec])
+        d = abs(out["logp"][i] - r.logp[i])
+        _say(f"snr {snr} {prec} image {i}: rho2 {rho2:.4f} |dlogP| {d:.3e} (bar {tol:.3e})")
+        assert d <= tol, (i, d, tol)
