@@ -169,6 +169,31 @@ bioem_status bioem_logpost(bioem_ctx* ctx, const bioem_proj* proj, const bioem_i
                            const double* ctf, int32_t nc, bioem_mem ctf_mem, int32_t max_shift,
                            const bioem_opts* opts, double* logp, bioem_best* best);
 
+/* Allocation-free form of bioem_logpost, for callers that cannot allocate
+ * device memory during the call (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc).  It computes exactly what
+ * bioem_logpost computes with opts = NULL except for where results go: plain
+ * F32 with the library's kernel choice, full orientation grid, no
+ * per-orientation output.
+ *   ctf [nc][3] float64 in HOST memory (validated there, then copied into
+ *   the scratch on the context's stream); logp [ni] float64 and best [ni] in
+ *   DEVICE memory on the context's device (either may be NULL).
+ * Every intermediate (CTF tables, projection norms, matrix-core operand
+ * tables, per-evaluation records) lives in one fixed 64 MiB scratch array
+ * per device, which the library holds from its load until the process ends;
+ * images are processed in chunks that fit it.  No hipMalloc, hipFree or
+ * event creation happens in the call (bioem_set_timing does not apply).
+ * Returns after enqueueing.  Every call on a device shares that device's
+ * scratch and leaves its contents behind: calls ordered on one stream are
+ * safe, calls that overlap on one GPU (other streams or contexts) race.
+ * Errors: as bioem_logpost, plus BIOEM_EUNSUPPORTED when the tables and one
+ * image's records (16 B per orientation x CTF set) exceed the 64 MiB, and
+ * BIOEM_EDEVICE when the scratch address could not be resolved at
+ * bioem_create. */
+bioem_status bioem_logpost_noalloc(bioem_ctx* ctx, const bioem_proj* proj, const bioem_imgs* imgs,
+                                   const double* ctf, int32_t nc, int32_t max_shift, double* logp,
+                                   bioem_best* best);
+
 /* One job of a batched call: a projection set and an image set of the same
  * box, their CTF grid and shift window, an optional proposal, and outputs.
  * Field meanings are those of bioem_logpost's arguments and options. */

@@ -6,6 +6,7 @@ builds it and marshals arguments to it.
 from .bindings import (  # noqa: F401
     Context, Projections, Images, BioemError, project, project_euler, prepare_images, logpost, render,
     ctf_from_physical, version, load, best_from_bytes, BEST_DTYPE, LIB_PATH, logpost_batch, Net, topk, cnn_input, ensemble, logpost_crop,
+    logpost_noalloc,
 )
 
 

@@ -95,6 +95,7 @@ SIGNATURES = [
     ("bioem_set_timing", _I, [_P, _I]),
     ("bioem_get_kernel_time", _I, [_P, ctypes.POINTER(_D), ctypes.POINTER(_I), ctypes.POINTER(_D)]),
     ("bioem_logpost_batch", _I, [_P, ctypes.POINTER(Job), _I, _I, _I, _I]),
+    ("bioem_logpost_noalloc", _I, [_P, _P, _P, _P, _I, _I, _P, _P]),
     ("bioem_set_autotune", _I, [_P, _I]),
     ("bioem_tuning_count", _I, [_P]),
     ("bioem_tuning_entry", _I, [_P, _I, ctypes.POINTER(Tuning)]),
@@ -321,6 +322,19 @@ def logpost(ctx: Context, proj: Projections, imgs: Images, ctf, max_shift: int,
     ctx.check(ctx._lib.bioem_logpost(ctx.h, proj.h, imgs.h, cp, nc, cm, max_shift, ctypes.byref(o),
                                      logp.ctypes.data, best.ctypes.data))
     return {"logp": logp, "best": best, "orient": orient_a}
+
+
+def logpost_noalloc(ctx: Context, proj: Projections, imgs: Images, ctf, max_shift: int, logp, best):
+    """bioem_logpost_noalloc: plain F32 log posterior written into the
+    caller's device tensors ``logp`` (float64 [ni]) and ``best`` (uint8
+    [ni * record size]); ``ctf`` is a host array.  Nothing is synchronised."""
+    ck = np.ascontiguousarray(ctf, dtype=np.float64)
+    if ck.ndim != 2 or ck.shape[1] != 3:
+        raise ValueError("ctf must be [nc][3]")
+    lp = logp.data_ptr() if logp is not None else None
+    bp = best.data_ptr() if best is not None else None
+    ctx.check(ctx._lib.bioem_logpost_noalloc(ctx.h, proj.h, imgs.h, ck.ctypes.data, int(ck.shape[0]),
+                                             int(max_shift), lp, bp))
 
 
 def logpost_batch(ctx: Context, jobs, prec: str = "split_f16", mode: str = "persistent",

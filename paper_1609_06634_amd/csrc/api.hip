@@ -6,6 +6,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -14,6 +15,34 @@
 
 using namespace bioem;
 using namespace bioem::host;
+
+// Scratch of bioem_logpost_noalloc: tables, norms and per-evaluation records
+// of one call.  Each device holds its own copy from the library's load to the
+// end of the process; host code reaches it only through the device address
+// that hipGetSymbolAddress returns for the current device (the array's name is
+// a host-side stand-in there).
+constexpr size_t kNoAllocBytes = size_t(64) << 20;
+static __device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch[kMaxDevices] = {};
+
+// The scratch address on `device`, resolved once per device with that device
+// current; nullptr when the runtime cannot give it.
+void* scratch_address(int device) {
+  if (device < 0 || device >= kMaxDevices) return nullptr;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch[device]) {
+    void* ptr = nullptr;
+    if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) == hipSuccess) g_scratch[device] = ptr;
+  }
+  return g_scratch[device];
+}
+
+}  // namespace
 
 namespace {
 
@@ -66,8 +95,11 @@ struct Job {
   Job(Job&&) = default;
 };
 
+// With a carve every device buffer of the job is a piece of it (nothing is
+// allocated): the CTF grid must then be host memory and the outputs device
+// memory.
 bioem_status plan_job(bioem_ctx* ctx, const bioem_job& jb, int prec, int out_mem, Job& J, const char* who,
-                      int kernel = 0, int ti = 0, int ts = 0) {
+                      int kernel = 0, int ti = 0, int ts = 0, Carve* carve = nullptr) {
   const bioem_proj* proj = jb.proj;
   const bioem_imgs* imgs = jb.imgs;
   if (!proj || !imgs || !jb.ctf) return fail(ctx, BIOEM_EINVAL, "%s: NULL handle or ctf", who);
@@ -88,9 +120,15 @@ bioem_status plan_job(bioem_ctx* ctx, const bioem_job& jb, int prec, int out_mem
   if (jb.cand_q && (jb.k < 1 || jb.k > nq))
     return fail(ctx, BIOEM_EINVAL, "%s: candidate count k=%d outside [1, %d]", who, jb.k, nq);
   hipStream_t s = ctx->stream;
-  std::vector<double> hc;
-  HIP_OR_FAIL(ctx, to_host(jb.ctf, (size_t)nc * 3, (bioem_mem)jb.ctf_mem, s, hc));
-  if (!finite_all(hc.data(), hc.size())) return fail(ctx, BIOEM_EINVAL, "%s: non-finite CTF value", who);
+  if (carve && (jb.ctf_mem != BIOEM_MEM_HOST || out_mem != BIOEM_MEM_DEVICE || jb.cand_q))
+    return fail(ctx, BIOEM_EINVAL, "%s: needs host CTF values, device outputs and no proposal", who);
+  std::vector<double> hcopy;
+  const double* hc = jb.ctf;
+  if (jb.ctf_mem != BIOEM_MEM_HOST) {
+    HIP_OR_FAIL(ctx, to_host(jb.ctf, (size_t)nc * 3, (bioem_mem)jb.ctf_mem, s, hcopy));
+    hc = hcopy.data();
+  }
+  if (!finite_all(hc, (size_t)nc * 3)) return fail(ctx, BIOEM_EINVAL, "%s: non-finite CTF value", who);
   for (int c = 0; c < nc; ++c)
     if (!(hc[3 * c + 1] >= 0.0 && hc[3 * c + 1] <= 1.0))
       return fail(ctx, BIOEM_EINVAL, "%s: amplitude contrast of CTF %d outside [0,1]", who, c);
@@ -140,19 +178,19 @@ bioem_status plan_job(bioem_ctx* ctx, const bioem_job& jb, int prec, int out_mem
   const int W = 2 * S + 1;
   J.log_prior = -std::log((double)nq) - std::log((double)nc) - std::log((double)W * W);
   J.len = (size_t)(nx / 2 + 1) * spec_ld(ny);
-  HIP_OR_FAIL(ctx, J.dctf.set(hc.data(), hc.size() * 8, BIOEM_MEM_HOST, s));
+  HIP_OR_FAIL(ctx, J.dctf.set(hc, (size_t)nc * 3 * 8, BIOEM_MEM_HOST, s, carve));
   if (J.has_cand) HIP_OR_FAIL(ctx, J.dcand.set(hcand.data(), hcand.size() * 4, BIOEM_MEM_HOST, s));
-  HIP_OR_FAIL(ctx, J.table.alloc(sizeof(float) * J.len * nc));
-  HIP_OR_FAIL(ctx, J.B.alloc(sizeof(double) * (size_t)nq * nc));
+  HIP_OR_FAIL(ctx, J.table.get(sizeof(float) * J.len * nc, carve));
+  HIP_OR_FAIL(ctx, J.B.get(sizeof(double) * (size_t)nq * nc, carve));
   HIP_OR_FAIL(ctx, launch_ctf_table(s, J.dctf.as<double>(), nc, nx, ny, proj->pixel, J.table.as<float>()));
   if (split) {
-    HIP_OR_FAIL(ctx, J.ttable.alloc(sizeof(float4) * tile_table_len(nx, ny) * nc));
+    HIP_OR_FAIL(ctx, J.ttable.get(sizeof(float4) * tile_table_len(nx, ny) * nc, carve));
     HIP_OR_FAIL(ctx, launch_tile_table(s, J.table.as<float>(), nc, nx, ny, J.ttable.as<float4>()));
   }
   if (mf) {
-    HIP_OR_FAIL(ctx, J.mftab.alloc(sizeof(float4) * mf32_table_len(nx, ny)));
+    HIP_OR_FAIL(ctx, J.mftab.get(sizeof(float4) * mf32_table_len(nx, ny), carve));
     HIP_OR_FAIL(ctx, launch_mf_tables(s, nx, ny, S, J.mftab.as<float4>()));
-    HIP_OR_FAIL(ctx, J.mftm.alloc(sizeof(float4) * mf_table_len(nx, ny) * nc));
+    HIP_OR_FAIL(ctx, J.mftm.get(sizeof(float4) * mf_table_len(nx, ny) * nc, carve));
     HIP_OR_FAIL(ctx, launch_mf_copy_table(s, J.table.as<float>(), nc, nx, ny, J.mftm.as<float4>()));
   }
   HIP_OR_FAIL(ctx, launch_proj_norms(s, proj->spec, proj->expo, nq, J.table.as<float>(), nc, nx, ny,
@@ -289,9 +327,10 @@ bioem_status split_cfg(bioem_ctx* ctx, const Job& J, int prec, SplitCfg& cfg) {
   return BIOEM_OK;
 }
 
-// One job: image chunks bounded by the record budget, main kernel, then the
-// FP64 finalisation of each chunk.
-bioem_status run_job(bioem_ctx* ctx, Job& J, int prec) {
+// One job: image chunks bounded by the record budget (by what is left of
+// the carve, when one is given), main kernel, then the FP64 finalisation of
+// each chunk.
+bioem_status run_job(bioem_ctx* ctx, Job& J, int prec, Carve* carve = nullptr) {
   hipStream_t s = ctx->stream;
   const bool split = prec != BIOEM_PREC_F32;
   SplitCfg cfg{0, 4, 0, 0};
@@ -300,23 +339,28 @@ bioem_status run_job(bioem_ctx* ctx, Job& J, int prec) {
     if (st != BIOEM_OK) return st;
   }
   const size_t per_image = sizeof(bioem_erec) * (size_t)J.nslots * J.nc;
-  const int chunk = (int)std::max<size_t>(1, std::min<size_t>(J.ni, kRecordBudget / per_image));
+  const size_t budget = carve ? carve->left() : kRecordBudget;
+  if (carve && budget < per_image)
+    return fail(ctx, BIOEM_EUNSUPPORTED, "bioem_logpost: records of one image (%zu B) exceed the scratch left (%zu B)",
+                per_image, budget);
+  const int chunk = (int)std::max<size_t>(1, std::min<size_t>(J.ni, budget / per_image));
   DevMem rec;
-  HIP_OR_FAIL(ctx, rec.alloc(per_image * chunk));
+  HIP_OR_FAIL(ctx, rec.get(per_image * chunk, carve));
   const int nchunks = (J.ni + chunk - 1) / chunk;
-  if (ctx->timing) {
+  const bool timing = ctx->timing && !carve;   // event creation stays out of the allocation-free form
+  if (timing) {
     const bioem_status st = ensure_events(ctx, nchunks);
     if (st != BIOEM_OK) return st;
   }
   for (int i0 = 0; i0 < J.ni; i0 += chunk) {
     const int cn = std::min(chunk, J.ni - i0);
     const LogpostArgs a = job_args(J, i0, cn, rec.as<bioem_erec>());
-    if (ctx->timing) HIP_OR_FAIL(ctx, hipEventRecord(ctx->ev_start[ctx->ev_used], s));
+    if (timing) HIP_OR_FAIL(ctx, hipEventRecord(ctx->ev_start[ctx->ev_used], s));
     hipError_t e = split  ? launch_logpost_split(s, a, prec == BIOEM_PREC_SPLIT_BF16, cfg.shape, cfg.ti, cfg.ts)
                    : J.mf ? launch_logpost_mf32(s, a, J.imgs->mf + mf_len(J.nx, J.ny) * i0, J.proj->mf,
                                                 J.mftm.as<float4>(), J.mftab.as<float4>(), J.ti, J.ts)
                           : launch_logpost_f32(s, a);
-    if (ctx->timing && e == hipSuccess) {
+    if (timing && e == hipSuccess) {
       HIP_OR_FAIL(ctx, hipEventRecord(ctx->ev_stop[ctx->ev_used], s));
       ++ctx->ev_used;
       ctx->timed_evals += (double)cn * J.nslots * J.nc;
@@ -415,6 +459,7 @@ bioem_status bioem_create(int device, void* hip_stream, bioem_ctx** out) {
   // NULL is the device's null (legacy default) stream, which other users of
   // that stream (e.g. a framework's default stream) are ordered with
   ctx->stream = static_cast<hipStream_t>(hip_stream);
+  ctx->scratch = scratch_address(device);
   *out = ctx;
   return BIOEM_OK;
 }
@@ -723,6 +768,42 @@ bioem_status bioem_logpost(bioem_ctx* ctx, const bioem_proj* proj, const bioem_i
   // Scratch (table, B, records) is freed on return, so the stream must drain.
   HIP_OR_FAIL(ctx, hipStreamSynchronize(ctx->stream));
   return BIOEM_OK;
+}
+
+bioem_status bioem_logpost_noalloc(bioem_ctx* ctx, const bioem_proj* proj, const bioem_imgs* imgs,
+                                   const double* ctf, int32_t nc, int32_t max_shift, double* logp,
+                                   bioem_best* best) {
+  if (!ctx) return BIOEM_EINVAL;
+  if (!ctx->scratch)
+    return fail(ctx, BIOEM_EDEVICE, "bioem_logpost_noalloc: scratch address of device %d unavailable", ctx->device);
+  if (proj && imgs) {
+    // the fixed tables and one image's records must fit
+    const size_t nq = (size_t)std::max(proj->n, 0), ncs = (size_t)std::max(nc, 0);
+    const size_t len = (size_t)(proj->nx / 2 + 1) * spec_ld(proj->ny);
+    const bool mf = nc > 0 && valid_box(proj->nx, proj->ny) && max_shift >= 0 &&
+                    2 * max_shift < std::min(proj->nx, proj->ny) && mf32_supported(proj->nx, proj->ny, max_shift);
+    size_t need = Carve::up(24 * ncs) + Carve::up(4 * len * ncs) + Carve::up(8 * nq * ncs) +
+                  Carve::up(sizeof(bioem_erec) * nq * ncs);
+    if (mf)
+      need += Carve::up(sizeof(float4) * mf32_table_len(proj->nx, proj->ny)) +
+              Carve::up(sizeof(float4) * mf_table_len(proj->nx, proj->ny) * ncs);
+    if (need > kNoAllocBytes)
+      return fail(ctx, BIOEM_EUNSUPPORTED,
+                  "bioem_logpost_noalloc: needs %zu bytes of scratch for %zu orientations x %zu CTF sets, more than "
+                  "its %zu",
+                  need, nq, ncs, kNoAllocBytes);
+  }
+  bioem_job jb{};
+  jb.proj = proj; jb.imgs = imgs; jb.ctf = ctf; jb.nc = nc; jb.ctf_mem = BIOEM_MEM_HOST; jb.max_shift = max_shift;
+  jb.logp = logp; jb.best = best;
+  HIP_OR_FAIL(ctx, hipSetDevice(ctx->device));
+  Carve carve;
+  carve.base = static_cast<char*>(ctx->scratch);
+  carve.cap = kNoAllocBytes;
+  Job J;
+  bioem_status st = plan_job(ctx, jb, BIOEM_PREC_F32, BIOEM_MEM_DEVICE, J, "bioem_logpost_noalloc", 0, 0, 0, &carve);
+  if (st != BIOEM_OK) return st;
+  return run_job(ctx, J, BIOEM_PREC_F32, &carve);
 }
 
 bioem_status bioem_logpost_batch(bioem_ctx* ctx, const bioem_job* jobs, int32_t njobs, int32_t prec,

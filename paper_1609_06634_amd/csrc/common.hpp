@@ -22,6 +22,9 @@ struct bioem_ctx {
   // tile shapes of the split kernel chosen by the autotuner, per key
   bool autotune = false;
   std::vector<bioem_tuning> tuned;
+  // device address of this device's copy of the allocation-free scratch
+  // (nullptr if it could not be resolved)
+  void* scratch = nullptr;
 };
 
 // Half spectra are stored column-major per item: spec[item][m][l] with

@@ -32,14 +32,37 @@ inline bioem_status fail(bioem_ctx* ctx, bioem_status st, const char* fmt, ...) 
                   #expr, hipGetErrorString(e_));                                            \
   } while (0)
 
-// Device buffer that frees itself.
+// Pieces of a fixed device region handed out in order (256-byte aligned,
+// never freed): the scratch of the allocation-free posterior.
+struct Carve {
+  char* base = nullptr;
+  size_t cap = 0, off = 0;
+  static size_t up(size_t v) { return (v + 255) & ~size_t(255); }
+  void* take(size_t bytes) {
+    const size_t o = up(off);
+    if (!base || o > cap || bytes > cap - o) return nullptr;
+    off = o + bytes;
+    return base + o;
+  }
+  size_t left() const { const size_t o = up(off); return o < cap ? cap - o : 0; }
+};
+
+// Device buffer that frees itself, or a piece of a Carve it does not own.
 struct DevMem {
   void* p = nullptr;
+  bool owned = true;
   DevMem() = default;
   DevMem(const DevMem&) = delete;
   DevMem& operator=(const DevMem&) = delete;
-  ~DevMem() { if (p) (void)hipFree(p); }
+  ~DevMem() { if (p && owned) (void)hipFree(p); }
   hipError_t alloc(size_t bytes) { return hipMalloc(&p, bytes ? bytes : 1); }
+  // from the carve when one is given (no allocation), else hipMalloc
+  hipError_t get(size_t bytes, Carve* c) {
+    if (!c) return alloc(bytes);
+    owned = false;
+    p = c->take(bytes ? bytes : 1);
+    return p ? hipSuccess : hipErrorOutOfMemory;
+  }
   template <class T> T* as() const { return static_cast<T*>(p); }
 };
 
@@ -48,10 +71,10 @@ struct DevMem {
 struct DevIn {
   DevMem own;
   const void* d = nullptr;
-  hipError_t set(const void* src, size_t bytes, bioem_mem mem, hipStream_t s) {
+  hipError_t set(const void* src, size_t bytes, bioem_mem mem, hipStream_t s, Carve* c = nullptr) {
     if (!src) { d = nullptr; return hipSuccess; }
     if (mem == BIOEM_MEM_DEVICE) { d = src; return hipSuccess; }
-    hipError_t e = own.alloc(bytes);
+    hipError_t e = own.get(bytes, c);
     if (e != hipSuccess) return e;
     d = own.p;
     return hipMemcpyAsync(own.p, src, bytes, hipMemcpyHostToDevice, s);

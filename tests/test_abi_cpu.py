@@ -65,6 +65,7 @@ def test_null_context_calls(lib):
     assert lib.bioem_ensemble(None, None, 1, 0, 0, None, None, None, 0) == P.bindings.BIOEM_EINVAL
     assert lib.bioem_logpost_crop(None, None, None, 1, 0, None, 1, 0, None, None, 0) == P.bindings.BIOEM_EINVAL
     assert lib.bioem_project_euler(None, None, 1, None, 1, 64, 64, 1.0, 0, None) == P.bindings.BIOEM_EINVAL
+    assert lib.bioem_logpost_noalloc(None, None, None, None, 1, 0, None, None) == P.bindings.BIOEM_EINVAL
 
 
 def test_create_without_device_fails_cleanly(lib):
