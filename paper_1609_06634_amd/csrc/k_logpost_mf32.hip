@@ -43,6 +43,7 @@
 // window maximum of X^2 and the FP32 sum of (1 + u)^-(n/2-1) relative to it;
 // the FP64 likelihood terms are added at finalisation.
 #include <algorithm>
+#include <type_traits>
 
 #include "common.hpp"
 
@@ -63,7 +64,7 @@ __host__ __device__ inline MfGeom mf_geom(int nx, int ny) {
   G.hasQ = ny % 4 == 0;
   G.Q = ny / 4;
   G.J1 = G.hasQ ? ny / 4 - 1 : (ny - 2) / 4;
-  G.KS1 = (G.J1 + 1 + 3) / 4;
+  G.KS1 = ((G.J1 + 1 + 3) / 4 + 1) & ~1;   // even: the K-steps are consumed in pairs
   G.Mx = nx / 2;
   G.hasQx = nx % 4 == 0;
   G.Qx = nx / 4;
@@ -257,7 +258,8 @@ struct MfArgs {
   int ti, ts, n_ti, n_ts;       // pair tile: images x orientation slots
 };
 
-constexpr int kMfWaves = 8;     // one workgroup per CU, two waves per SIMD
+constexpr int kMfWaves = 4;     // one wave per SIMD in a workgroup
+constexpr int kMfBlocksPerCU = 3; // three workgroups per CU: three waves per SIMD (at most 168 VGPRs)
 constexpr int kSlotF4 = 136;    // one produced K-step in LDS: [2][64 lanes] float4 + [2][4] (packed column)
 
 __device__ __forceinline__ f4 mma(float a, float b, f4 c) {
@@ -342,13 +344,20 @@ __device__ __forceinline__ Ops ops_special(float4 x0, float4 x1, float4 t, float
 // pass * wpp + w % wpp of pair w / wpp.  The folded products conj(I) P of each
 // K-step are made once per pair (each wave makes one K-step of a round) and
 // read by the pair's waves from LDS; every wave then applies its own CTF set.
-__global__ __launch_bounds__(64 * kMfWaves) void k_logpost_mf32(MfArgs ma) {
+//
+// The consumed steps run half group by half group, two K-steps at a time
+// (KS1 is even), with the cases that differ resolved at compile time: the
+// first K-step of a half group holds the shared slot (points 0, N/4, H,
+// 3N/4) in its lanes g = 0, and the first half group carries the packed
+// slot's second column (x = nx/2) in lanes p = 0.  The CTF values of a step
+// are loaded two steps ahead into one of two register sets.
+__global__ __launch_bounds__(64 * kMfWaves, kMfBlocksPerCU) void k_logpost_mf32(MfArgs ma) {
   extern __shared__ float4 lds_mf[];
   const int n1 = ma.KS1 * 64, n2 = ma.nHG * 128;
   float4* const F1s = lds_mf;
   float4* const F2s = lds_mf + n1;
-  float4* const slots = F2s + n2;                          // [2][8][kSlotF4]
-  float4* const stage = slots + 2 * 8 * kSlotF4;           // [8 waves][16]
+  float4* const slots = F2s + n2;                          // [2][kMfWaves][kSlotF4]
+  float4* const stage = slots + 2 * kMfWaves * kSlotF4;    // [kMfWaves][16]
   for (int e = threadIdx.x; e < n1 + n2; e += 64 * kMfWaves) lds_mf[e] = e < n1 ? ma.F1[e] : ma.F2[e - n1];
   __syncthreads();
 
@@ -356,12 +365,13 @@ __global__ __launch_bounds__(64 * kMfWaves) void k_logpost_mf32(MfArgs ma) {
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int KS1 = ma.KS1, nHG = ma.nHG, nsteps = KS1 * nHG;
   const int G = ma.G, wpp = ma.wpp, R = ma.R, passes = ma.passes;
-  const int nrounds = (nsteps + R - 1) / R;
+  const int lgR = __builtin_ctz(R);   // R is a power of two
+  const int nrounds = (nsteps + R - 1) >> lgR;
   const int nslots = ma.cand ? ma.k : ma.nq;
   const int S = ma.S;
   const size_t main_len = (size_t)nHG * KS1 * 128, tmain = (size_t)nHG * KS1 * 64;
   // producer role: K-step w % R of each round for pair w / R of the group
-  const int gp_p = w / R, kp = w - gp_p * R;
+  const int gp_p = w >> lgR, kp = w & (R - 1);
   // consumer role
   const int gi = w / wpp, cw = w - gi * wpp;
 
@@ -409,22 +419,22 @@ __global__ __launch_bounds__(64 * kMfWaves) void k_logpost_mf32(MfArgs ma) {
       // one float4 per lane of the first 16), then its folded products
       float4 pf0, pf1, pf2, pf3, pfs;
       auto load = [&](int rr) {
-        const int st = rr * R + kp;
+        const int st = (rr << lgR) + kp;
         if (st < nsteps) {
           const size_t o = ((size_t)st * 64 + lane) * 2;
           pf0 = Ib[o]; pf1 = Ib[o + 1]; pf2 = Pb[o]; pf3 = Pb[o + 1];
           if (st < KS1 && lane < 16) {   // first half group: the packed slot
-            const int s1 = st, gs = lane >> 2, which = lane & 3;
-            const size_t os = main_len + ((size_t)s1 * 4 + gs) * 2 + (which & 1);
+            const int gs = lane >> 2, which = lane & 3;
+            const size_t os = main_len + ((size_t)st * 4 + gs) * 2 + (which & 1);
             pfs = which < 2 ? Ib[os] : Pb[os];
           }
         }
       };
       auto produce = [&](int rr) {
-        const int st = rr * R + kp;
+        const int st = (rr << lgR) + kp;
         if (st >= nsteps) return;   // uniform per wave
         const int s1 = st % KS1;
-        float4* sl = slots + ((rr & 1) * 8 + w) * kSlotF4;
+        float4* sl = slots + ((rr & 1) * kMfWaves + w) * kSlotF4;
         float4 o0, o1;
         fold_w(pf0, pf1, pf2, pf3, o0, o1);
         if (s1 == 0) {   // uniform: lanes g = 0 hold the shared slot
@@ -446,6 +456,16 @@ __global__ __launch_bounds__(64 * kMfWaves) void k_logpost_mf32(MfArgs ma) {
           }
         }
       };
+      // start of round rr >= 1: every wave has consumed round rr - 1 and made
+      // round rr; make round rr + 1 in the freed buffer, load round rr + 2
+      auto boundary = [&](int st) {
+        if ((st & (R - 1)) == 0 && st > 0) {   // uniform
+          const int rr = st >> lgR;
+          __syncthreads();
+          if (rr + 1 < nrounds) produce(rr + 1);
+          if (rr + 2 < nrounds) load(rr + 2);
+        }
+      };
 
       f4 d2[2][8];
 #pragma unroll
@@ -459,8 +479,9 @@ __global__ __launch_bounds__(64 * kMfWaves) void k_logpost_mf32(MfArgs ma) {
         for (int b = 0; b < 4; ++b) d1[tt][b] = f4{0.f, 0.f, 0.f, 0.f};
       float cre = 0.f, cim = 0.f;
 
-      // stage 2 of half group h (its stage-1 accumulators are complete)
-      auto stage2 = [&](int h) {
+      // stage 2 of half group h (its stage-1 accumulators are complete);
+      // FIRST: h = 0, whose pair 0 is the packed slot and the column nx/4
+      auto stage2 = [&](auto FIRST, int h) {
         // even rows: + (-1)^p (W(N/4) + W(3N/4)) T(N/4) of each column
         const float sg = (p & 1) ? -1.0f : 1.0f;
 #pragma unroll
@@ -479,8 +500,8 @@ __global__ __launch_bounds__(64 * kMfWaves) void k_logpost_mf32(MfArgs ma) {
             const int ra = 2 * h2, rb = 2 * h2 + 1;
             float URp = Ur[ra] + Ur[rb], URm = Ur[ra] - Ur[rb], UIp = Ui[ra] + Ui[rb], UIm = Ui[ra] - Ui[rb];
             float VRp = Vr[ra] + Vr[rb], VRm = Vr[ra] - Vr[rb], VIp = Vi[ra] + Vi[rb], VIm = Vi[ra] - Vi[rb];
-            if (h == 0 && h2 == 0) {   // uniform
-              if (g == 0) {            // pair 0: packed slot (member 0) and column nx/4 (member 1)
+            if constexpr (decltype(FIRST)::value) {
+              if (h2 == 0 && g == 0) {   // pair 0: packed slot (member 0) and column nx/4 (member 1)
                 a0u = Ur[ra] + Ui[ra];
                 a0v = Vi[ra] - Vr[ra];
                 URm = Ur[ra] - Ui[ra];
@@ -503,7 +524,7 @@ __global__ __launch_bounds__(64 * kMfWaves) void k_logpost_mf32(MfArgs ma) {
             d2[s][6] = mma(Af.w, UIp, d2[s][6]);
             d2[s][7] = mma(Af.w, VRp, d2[s][7]);
           }
-          if (h == 0) {   // a(0) = Y(0) + Y(nx/2), weight 1 at every even dx
+          if constexpr (decltype(FIRST)::value) {   // a(0) = Y(0) + Y(nx/2), weight 1 at every even dx
             const float xu = __shfl(a0u, p, 64), xv = __shfl(a0v, p, 64);
 #pragma unroll
             for (int rr = 0; rr < 4; ++rr) {
@@ -520,37 +541,34 @@ __global__ __launch_bounds__(64 * kMfWaves) void k_logpost_mf32(MfArgs ma) {
         cim = 0.f;
       };
 
-      // one consumed K-step: sl is its LDS slot, tc / ts its CTF values; the
-      // next step's CTF values are loaded into tn / tsn
-      auto step = [&](int st, int h, int s1, const float4* sl, const float4& tc, const float4& tsc, float4& tn,
-                      float4& tsn) {
-        if (st + 1 < nsteps) {
-          tn = Tb[(size_t)(st + 1) * 64 + lane];
-          if (st + 1 < KS1) {   // uniform
-            if (p == 0) tsn = Tb[tmain + (size_t)(st + 1) * 4 + g];
-          }
-        }
+      // one consumed K-step st (K-step s1 of its half group); tc / tsc hold
+      // its CTF values and receive those of step st + 2.  PK: first half
+      // group (packed slot); SP: s1 = 0 (shared slot in lanes g = 0).
+      auto step = [&](auto PK, auto SP, int st, int s1, float4& tc, float4& tsc) {
+        constexpr bool kPK = decltype(PK)::value, kSP = decltype(SP)::value;
+        const int rr = st >> lgR;
+        const float4* sl = slots + ((rr & 1) * kMfWaves + gi * R + (st & (R - 1))) * kSlotF4;
         const float4 x0 = sl[lane], x1 = sl[64 + lane], bf = F1s[s1 * 64 + lane];
         Ops o;
-        if (s1 == 0) {   // uniform: lanes g = 0 hold the shared slot
+        if constexpr (kSP) {
           float cr = 0.f, ci = 0.f;
           const Ops a = ops_regular(x0, x1, tc), b = ops_special(x0, x1, tc, cr, ci);
-          const bool sp = g == 0;
-          o.u0r = sp ? b.u0r : a.u0r; o.u0i = sp ? b.u0i : a.u0i;
-          o.v0r = sp ? b.v0r : a.v0r; o.v0i = sp ? b.v0i : a.v0i;
-          o.u1r = sp ? b.u1r : a.u1r; o.u1i = sp ? b.u1i : a.u1i;
-          o.v1r = sp ? b.v1r : a.v1r; o.v1i = sp ? b.v1i : a.v1i;
-          cre = sp ? cr : 0.f;
-          cim = sp ? ci : 0.f;
+          const bool spl = g == 0;
+          o.u0r = spl ? b.u0r : a.u0r; o.u0i = spl ? b.u0i : a.u0i;
+          o.v0r = spl ? b.v0r : a.v0r; o.v0i = spl ? b.v0i : a.v0i;
+          o.u1r = spl ? b.u1r : a.u1r; o.u1i = spl ? b.u1i : a.u1i;
+          o.v1r = spl ? b.v1r : a.v1r; o.v1i = spl ? b.v1i : a.v1i;
+          cre = spl ? cr : 0.f;
+          cim = spl ? ci : 0.f;
         } else {
           o = ops_regular(x0, x1, tc);
         }
-        if (__builtin_amdgcn_readfirstlane(h) == 0) {   // uniform
+        if constexpr (kPK) {
           if (p == 0) {  // packed slot: + i x (the column nx/2)
             const float4 y0 = sl[128 + g], y1 = sl[132 + g];
             Ops m;
             float cr = 0.f, ci = 0.f;
-            if (s1 == 0 && g == 0) m = ops_special(y0, y1, tsc, cr, ci);
+            if (kSP && g == 0) m = ops_special(y0, y1, tsc, cr, ci);
             else m = ops_regular(y0, y1, tsc);
             o.u0r -= m.u0i; o.u0i += m.u0r;
             o.v0r -= m.v0i; o.v0i += m.v0r;
@@ -558,6 +576,14 @@ __global__ __launch_bounds__(64 * kMfWaves) void k_logpost_mf32(MfArgs ma) {
             o.v1r -= m.v1i; o.v1i += m.v1r;
             cre -= ci; cim += cr;
           }
+        }
+        // this register set now takes the CTF values of step st + 2 (the
+        // load is unconditional, clamped to the last step, so that no copy
+        // of the old values has to wait for it)
+        {
+          const int sn = min(st + 2, nsteps - 1);
+          tc = Tb[(size_t)sn * 64 + lane];
+          if constexpr (kPK) tsc = Tb[tmain + (size_t)min(st + 2, KS1 - 1) * 4 + g];
         }
         d1[0][0] = mma(o.u0r, bf.x, d1[0][0]);
         d1[1][0] = mma(o.u0i, bf.x, d1[1][0]);
@@ -567,40 +593,54 @@ __global__ __launch_bounds__(64 * kMfWaves) void k_logpost_mf32(MfArgs ma) {
         d1[1][2] = mma(o.u1i, bf.z, d1[1][2]);
         d1[0][3] = mma(o.v1r, bf.w, d1[0][3]);
         d1[1][3] = mma(o.v1i, bf.w, d1[1][3]);
-        if (s1 == KS1 - 1) stage2(h);   // uniform: half group h done
       };
 
-      // CTF values of the consumed K-steps, one step ahead, in two register
-      // sets used alternately (steps are taken in pairs)
-      float4 ta = Tb[lane], tsa = make_float4(0.f, 0.f, 0.f, 0.f), tb = ta, tsb = tsa;
-      if (p == 0) tsa = Tb[tmain + g];
+      // CTF values of steps 0 and 1 (KS1 >= 2), in the two register sets
+      float4 ta = Tb[lane], tb = Tb[64 + lane];
+      float4 tsa = make_float4(0.f, 0.f, 0.f, 0.f), tsb = tsa;
+      if (p == 0) {
+        tsa = Tb[tmain + g];
+        tsb = Tb[tmain + 4 + g];
+      }
 
       load(0);
       produce(0);
       if (nrounds > 1) load(1);
       __syncthreads();
-      int h = 0, s1 = 0;   // half group and K-step of the next consumed step
-      for (int r = 0; r < nrounds; ++r) {
-        if (r + 1 < nrounds) produce(r + 1);
-        if (r + 2 < nrounds) load(r + 2);
-        const int st0 = r * R, st1 = min(st0 + R, nsteps);
-        const float4* sl = slots + ((r & 1) * 8 + gi * R) * kSlotF4;
-        int st = st0;
-        for (; st + 1 < st1; st += 2) {
-          step(st, h, s1, sl, ta, tsa, tb, tsb);
-          if (++s1 == KS1) { s1 = 0; ++h; }
-          step(st + 1, h, s1, sl + kSlotF4, tb, tsb, ta, tsa);
-          if (++s1 == KS1) { s1 = 0; ++h; }
-          sl += 2 * kSlotF4;
-        }
-        if (st < st1) {   // odd step count: the values move back to set a
-          step(st, h, s1, sl, ta, tsa, tb, tsb);
-          if (++s1 == KS1) { s1 = 0; ++h; }
-          ta = tb;
-          tsa = tsb;
-        }
-        __syncthreads();
+      if (nrounds > 1) produce(1);
+      if (nrounds > 2) load(2);
+
+      using T_ = std::integral_constant<bool, true>;
+      using F_ = std::integral_constant<bool, false>;
+      const bool r1 = R == 1;   // a round boundary can fall on an odd step
+      // first half group
+      boundary(0);
+      step(T_{}, T_{}, 0, 0, ta, tsa);
+      if (r1) boundary(1);
+      step(T_{}, F_{}, 1, 1, tb, tsb);
+      int st = 2;
+      for (int s1 = 2; s1 < KS1; s1 += 2, st += 2) {
+        boundary(st);
+        step(T_{}, F_{}, st, s1, ta, tsa);
+        if (r1) boundary(st + 1);
+        step(T_{}, F_{}, st + 1, s1 + 1, tb, tsb);
       }
+      stage2(T_{}, 0);
+      for (int h = 1; h < nHG; ++h) {
+        boundary(st);
+        step(F_{}, T_{}, st, 0, ta, tsa);
+        if (r1) boundary(st + 1);
+        step(F_{}, F_{}, st + 1, 1, tb, tsb);
+        st += 2;
+        for (int s1 = 2; s1 < KS1; s1 += 2, st += 2) {
+          boundary(st);
+          step(F_{}, F_{}, st, s1, ta, tsa);
+          if (r1) boundary(st + 1);
+          step(F_{}, F_{}, st + 1, s1 + 1, tb, tsb);
+        }
+        stage2(F_{}, h);
+      }
+      __syncthreads();   // the last round's slots are read before the next group makes round 0
 
       // epilogue of this wave's evaluation (image ic, orientation qc, CTF c)
       const double A = ma.istats[3 * ic + 2];
@@ -613,13 +653,17 @@ __global__ __launch_bounds__(64 * kMfWaves) void k_logpost_mf32(MfArgs ma) {
       // X at (+-k, +-dx) from the eight stage-2 products, squared in place
       // (-1 marks slots outside the window and the duplicates of k = 0, dx = 0)
       float x2max = 0.0f;
+      // the window masks are recomputed here, not kept live across the loops
+      // (hoisted, they would hold 64 scalar registers)
+      int pe = p, ge = g;
+      asm volatile("" : "+v"(pe), "+v"(ge));
 #pragma unroll
       for (int s = 0; s < 2; ++s) {
-        const int kk = 2 * p + s;
+        const int kk = 2 * pe + s;
         const bool kpos = kk <= S, kneg = kpos && kk > 0;
 #pragma unroll
         for (int rr = 0; rr < 4; ++rr) {
-          const int rho = 4 * g + rr;
+          const int rho = 4 * ge + rr;
           const bool ap = 2 * rho <= S, am = ap && rho > 0, bp = 2 * rho + 1 <= S;
           const float Eap = d2[s][0][rr] - d2[s][1][rr], Eam = d2[s][0][rr] + d2[s][1][rr];
           const float Oap = d2[s][2][rr] + d2[s][3][rr], Oam = d2[s][2][rr] - d2[s][3][rr];
@@ -708,7 +752,7 @@ size_t mf_table_len(int nx, int ny) { return mf_tab_len(mf_geom(nx, ny)); }
 
 size_t mf32_smem_bytes(int nx, int ny) {
   const MfGeom G = mf_geom(nx, ny);
-  return sizeof(float4) * ((size_t)G.KS1 * 64 + (size_t)G.nHG * 128 + 2 * 8 * kSlotF4 + kMfWaves * 16);
+  return sizeof(float4) * ((size_t)G.KS1 * 64 + (size_t)G.nHG * 128 + 2 * kMfWaves * kSlotF4 + kMfWaves * 16);
 }
 
 bool mf32_supported(int nx, int ny, int S) {
@@ -762,7 +806,7 @@ hipError_t launch_logpost_mf32(hipStream_t s, const LogpostArgs& a, const float4
   ma.KS1 = G.KS1;
   ma.nHG = G.nHG;
   // waves per pair: the CTF sets of one pair share its products (a power of
-  // two up to 8, so a group of pairs fills the workgroup)
+  // two up to the workgroup's wave count, so a group of pairs fills it)
   int wpp = 1;
   while (wpp < a.nc && wpp < kMfWaves) wpp *= 2;
   ma.wpp = wpp;
@@ -782,7 +826,7 @@ hipError_t launch_logpost_mf32(hipStream_t s, const LogpostArgs& a, const float4
   hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_logpost_mf32),
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
   if (e != hipSuccess) return e;
-  const int grid = (int)std::min<long>(groups, (long)mf_device_cus());
+  const int grid = (int)std::min<long>(groups, (long)kMfBlocksPerCU * mf_device_cus());
   hipLaunchKernelGGL(k_logpost_mf32, dim3(grid), dim3(64 * kMfWaves), smem, s, ma);
   return hipGetLastError();
 }
