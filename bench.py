@@ -133,24 +133,25 @@ def log(msg: str):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def cpu_baseline(sample: str):
-    """Time the FP64 oracle on a bounded sample of the same workload."""
+def cpu_baseline(sample: str, method: str = "fft"):
+    """Time the FP64 oracle on a bounded sample of the same workload.
+
+    method "fft": the correlation window by FP64 FFTs (numpy), the paper's
+    own CPU formulation; "direct": the direct circular correlation."""
     import numpy as np
     import oracle as O
     from workloads import make_workload
-    try:
-        from threadpoolctl import threadpool_info
-        threads = max([t.get("num_threads", 1) for t in threadpool_info()] or [1])
-    except Exception:  # pragma: no cover
-        threads = 1
     ni, nq, nc = (int(x) for x in sample.split("x"))
     wl = make_workload(2, n_images=ni)
     cls = wl.classes[0]
     imgs = O.render_images(cls, wl.models)
-    t0 = time.perf_counter()
+    t0, c0 = time.perf_counter(), time.process_time()
     O.logpost_oracle(imgs, wl.models[0], cls.quats[:nq], cls.ctf[:nc], cls.pixel_A, cls.max_shift,
-                     method="direct")
-    dt = time.perf_counter() - t0
+                     method=method)
+    dt, cpu_s = time.perf_counter() - t0, time.process_time() - c0
+    # cores actually used: the process's CPU time over the wall time (numpy's
+    # FFT is single-threaded; its matrix products may use several threads)
+    threads = max(1.0, round(cpu_s / dt, 1))
     evals = ni * nq * nc
     cpu = "unknown"
     try:
@@ -162,7 +163,8 @@ def cpu_baseline(sample: str):
         pass
     return {"value": evals / dt, "unit": "evals/s", "cores": threads, "kind": "oracle",
             "sample": f"{ni} images x {nq} orientations x {nc} CTF sets of the 224^2 workload, "
-                      f"all 1681 shifts, direct FP64 correlation; {dt:.1f} s on {cpu} "
+                      f"all 1681 shifts, FP64 {'FFT' if method == 'fft' else 'direct'} correlation; "
+                      f"{dt:.1f} s on {cpu} "
                       f"(os.cpu_count()={os.cpu_count()})"}
 
 
@@ -174,7 +176,10 @@ def main() -> int:
     ap.add_argument("--prec", default="f32", choices=["f32", "split_f16", "split_bf16"])
     ap.add_argument("--images", type=int, default=1000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample", default="2x8x2")
+    ap.add_argument("--cpu-sample", default="16x48x8",
+                    help="images x orientations x CTF sets for the oracle's FFT form")
+    ap.add_argument("--cpu-sample-direct", default="2x8x2",
+                    help="the same for the oracle's direct correlation")
     ap.add_argument("--workload", default="paper224", choices=["paper224", "mixed", "proposal", "crossover"],
                     help="paper224: 224^2, 1000 images x 4608 orientations x 8 CTF sets (default); "
                          "mixed: 96/128/180/224 px classes x two models in one persistent launch; "
@@ -318,8 +323,10 @@ def main() -> int:
             "dlogp_vs_fp64": dlogp,
             "ms_per_call": {k: round(v / args.steps * 1e3, 3) for k, v in calls.items()}}
     if not args.no_cpu_baseline:
-        log(f"timing the CPU oracle on a {args.cpu_sample} sample")
-        line["cpu_baseline"] = cpu_baseline(args.cpu_sample)
+        log(f"timing the CPU oracle (FFT form) on a {args.cpu_sample} sample")
+        line["cpu_baseline"] = cpu_baseline(args.cpu_sample, "fft")
+        log(f"timing the CPU oracle (direct form) on a {args.cpu_sample_direct} sample")
+        line["cpu_baseline_direct"] = cpu_baseline(args.cpu_sample_direct, "direct")
     print(json.dumps(line), flush=True)
     ctx.close()
     return 0
