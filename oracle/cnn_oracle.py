@@ -187,3 +187,20 @@ def top_k(z: np.ndarray, K: int):
         e = np.exp(row - row.max())
         mass[b] = e[order].sum() / e.sum()
     return out, mass
+
+
+def adam_step(w: np.ndarray, g: np.ndarray, m: np.ndarray, v: np.ndarray, t: int, lr: float, beta1: float,
+              beta2: float, eps: float):
+    """One Adam update with bias correction (Kingma and Ba, "Adam: a method
+    for stochastic optimization", ICLR 2015, Algorithm 1), in FP64; t is the
+    1-based step count.  The moments are exponential averages of g and g^2,
+    divided by 1 - beta^t so that they are unbiased from a zero start; the
+    parameter moves by lr times their ratio.  Returns (w, m, v) after the
+    step; the inputs are not modified."""
+    w = np.asarray(w, np.float64)
+    g = np.asarray(g, np.float64)
+    m = beta1 * np.asarray(m, np.float64) + (1.0 - beta1) * g
+    v = beta2 * np.asarray(v, np.float64) + (1.0 - beta2) * g * g
+    m_hat = m / (1.0 - beta1 ** t)
+    v_hat = v / (1.0 - beta2 ** t)
+    return w - lr * m_hat / (np.sqrt(v_hat) + eps), m, v

@@ -93,3 +93,56 @@ def test_network_input_is_the_autocorrelation():
     # a circular shift of the particle leaves the input unchanged
     shifted = np.roll(img, (3, -2), axis=(1, 2))
     np.testing.assert_allclose(C.network_input(shifted), got, atol=1e-12)
+
+
+# ---- Adam (the optimiser of the proposal network) ------------------------
+
+def test_adam_first_step_moves_each_weight_by_lr():
+    """From zero moments the bias-corrected moments of step 1 are g and g^2
+    exactly, so every weight moves by lr * g / (|g| + eps): lr against the
+    gradient's sign wherever |g| >> eps, whatever beta1 and beta2 are."""
+    rng = np.random.default_rng(11)
+    w = rng.standard_normal(1000)
+    g = rng.standard_normal(1000) * 10.0 ** rng.uniform(-4, 2, 1000)
+    for b1, b2 in [(0.9, 0.999), (0.5, 0.9), (0.0, 0.0)]:
+        w1, m1, v1 = C.adam_step(w, g, np.zeros_like(w), np.zeros_like(w), 1, 0.01, b1, b2, 1e-12)
+        np.testing.assert_allclose(w - w1, 0.01 * g / (np.abs(g) + 1e-12), rtol=1e-12)
+        assert np.all(np.abs(np.abs(w - w1) - 0.01) <= 0.01 * 1e-12 / np.abs(g) + 1e-15 * (1 + np.abs(w)))
+        np.testing.assert_allclose(m1, (1 - b1) * g, rtol=1e-15)
+        np.testing.assert_allclose(v1, (1 - b2) * g * g, rtol=1e-15)
+
+
+def test_adam_constant_gradient_takes_equal_steps():
+    """With the same gradient every step the corrected moments stay g and
+    g^2 (the corrections 1 - beta^t cancel the zero start exactly), so t
+    steps move a weight by t * lr against the sign; a wrong power of beta in
+    the correction breaks this from step 2 on."""
+    rng = np.random.default_rng(12)
+    w0 = rng.standard_normal(50)
+    g = rng.standard_normal(50)
+    w, m, v = w0, np.zeros(50), np.zeros(50)
+    for t in range(1, 11):
+        w, m, v = C.adam_step(w, g, m, v, t, 1e-3, 0.8, 0.95, 1e-12)
+        np.testing.assert_allclose(w0 - w, t * 1e-3 * np.sign(g), rtol=1e-9)
+
+
+def test_adam_moment_decay_and_zero_gradient():
+    """After one step with gradient g, zero gradients leave the raw moments
+    decaying as beta1^k and beta2^k (which catches swapped betas), and the
+    update as the ratio of their corrected values; a zero gradient from zero
+    moments moves nothing."""
+    g = np.array([2.0, -0.5])
+    w, m, v = C.adam_step(np.zeros(2), g, np.zeros(2), np.zeros(2), 1, 0.1, 0.9, 0.99, 0.0)
+    for k in range(1, 4):
+        w_new, m, v = C.adam_step(w, np.zeros(2), m, v, 1 + k, 0.1, 0.9, 0.99, 0.0)
+        np.testing.assert_allclose(m, 0.9 ** k * 0.1 * g, rtol=1e-14)
+        np.testing.assert_allclose(v, 0.99 ** k * 0.01 * g * g, rtol=1e-14)
+        mh = m / (1 - 0.9 ** (1 + k))
+        vh = v / (1 - 0.99 ** (1 + k))
+        ratio = (0.9 ** k * 0.1 / (1 - 0.9 ** (1 + k))) / np.sqrt(0.99 ** k * 0.01 / (1 - 0.99 ** (1 + k)))
+        np.testing.assert_allclose(w - w_new, 0.1 * np.sign(g) * ratio, rtol=1e-12)
+        np.testing.assert_allclose(mh / np.sqrt(vh), np.sign(g) * ratio, rtol=1e-12)
+        w = w_new
+    w0 = np.array([0.3, -1.2])
+    w1, _, _ = C.adam_step(w0, np.zeros(2), np.zeros(2), np.zeros(2), 1, 0.1, 0.9, 0.999, 1e-8)
+    assert np.array_equal(w1, w0)
