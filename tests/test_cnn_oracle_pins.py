@@ -146,3 +146,53 @@ def test_adam_moment_decay_and_zero_gradient():
     w0 = np.array([0.3, -1.2])
     w1, _, _ = C.adam_step(w0, np.zeros(2), np.zeros(2), np.zeros(2), 1, 0.1, 0.9, 0.999, 1e-8)
     assert np.array_equal(w1, w0)
+
+
+# ---- the element-wise error bounds of the network parity tests -----------
+
+def _bound_case():
+    import cnn_bounds as CB
+    arch = C.Arch(box=32, c1=4, c2=8, c3=8, c4=8, hidden=8, nq=50)
+    rng = np.random.default_rng(21)
+    parts = []
+    for name, shape in arch.shapes():   # He-style scale, as the network is trained from
+        scale = np.sqrt(2.0 / np.prod(shape[1:])) if name[0] in "WF" else 0.1
+        parts.append(rng.standard_normal(int(np.prod(shape))) * scale)
+    flat = np.concatenate(parts).astype(np.float32).astype(np.float64)
+    imgs = (rng.standard_normal((5, 32, 32)) + np.linspace(0, 3, 32)[None, None, :]).astype(np.float32)
+    tidx, tp = _targets(5, arch.nq, 4, 22)
+    return CB, arch, flat, imgs, tidx, tp
+
+
+def test_bf16_rounding_emulation():
+    import cnn_bounds as CB
+    x = np.array([1.0, 1.0 + 2.0 ** -8, 1.0 + 3 * 2.0 ** -8, -2.5, 1e-20, 3.0e38])
+    r = CB.bf16_round(x)
+    # ties to even: 1 + 2^-8 -> 1, 1 + 3 2^-8 -> 1 + 2^-6 (= 1 + 4 2^-8)
+    np.testing.assert_array_equal(r[:4], [1.0, 1.0, 1.0 + 2.0 ** -6, -2.5])
+    rng = np.random.default_rng(3)
+    v = rng.standard_normal(10000) * 10.0 ** rng.uniform(-10, 10, 10000)
+    rv = CB.bf16_round(v)
+    assert np.all(np.abs(rv - v.astype(np.float32)) <= 2.0 ** -8 * np.abs(v) * (1 + 1e-6))
+    assert np.all((rv.astype(np.float32).view(np.uint32) & 0xFFFF) == 0)
+
+
+def test_network_bounds_hold_for_emulated_bf16_products():
+    """The element-wise bounds of logits and gradients contain the deviation
+    of a recomputation whose products take bf16-rounded operands; with
+    operands rounded to 5 bits instead, some elements leave them."""
+    CB, arch, flat, imgs, tidx, tp = _bound_case()
+    loss, g, z, Eloss, Eg, Ez = CB.grad_bound(arch, flat, imgs, tidx, tp)
+    lr, gr = C.loss_and_grad(arch, flat, imgs, tidx, tp)
+    np.testing.assert_allclose(g, gr, rtol=1e-12, atol=1e-15)   # same reference
+    le, ge, ze = CB.emulate_loss_and_grad(arch, flat, imgs, tidx, tp, bits=8)
+    assert np.all(np.abs(ze - z) <= Ez)
+    assert np.all(np.abs(ge - g) <= Eg)
+    assert abs(le - loss) <= Eloss
+    # the bounds have teeth: operands rounded to 6 bits (errors 4x those of
+    # bf16) already leave them somewhere, and 5 bits in many places
+    _, g6, z6 = CB.emulate_loss_and_grad(arch, flat, imgs, tidx, tp, bits=6)
+    assert np.any(np.abs(z6 - z) > Ez) or np.any(np.abs(g6 - g) > Eg)
+    _, g5, z5 = CB.emulate_loss_and_grad(arch, flat, imgs, tidx, tp, bits=5)
+    assert np.sum(np.abs(z5 - z) > Ez) + np.sum(np.abs(g5 - g) > Eg) > 20
+    assert np.median(Ez / np.maximum(np.abs(z), 1e-30)) < 0.2

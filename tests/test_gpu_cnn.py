@@ -13,6 +13,8 @@ import pytest
 
 from oracle import cnn_oracle as C
 
+import cnn_bounds as CB
+
 pytestmark = pytest.mark.gpu
 
 SMALL = C.Arch(box=32, c1=4, c2=8, c3=8, c4=8, hidden=8, nq=50)
@@ -69,6 +71,7 @@ def _rel(a, b):
 
 
 def test_forward_matches_reference(P, ctx):
+    """Logits element by element within the bf16-product bound (cnn_bounds)."""
     arch = SMALL
     net = _net(P, ctx, arch)
     w = _init(arch, 1)
@@ -76,30 +79,31 @@ def test_forward_matches_reference(P, ctx):
     assert np.array_equal(net.get_params(), w)
     imgs, _, _ = _data(arch, 6, 3, 2)
     z = net.forward(imgs)
-    zr, _ = C.forward(arch, w.astype(np.float64), imgs)
-    _say(f"forward rel err {_rel(z, zr):.2e}")
-    assert _rel(z, zr) < 2e-2
+    zr, vz, Dz, _ = CB.forward_bound(arch, w.astype(np.float64), imgs)
+    Ez = CB.bound(vz, Dz)
+    r = np.abs(z - zr) / Ez
+    _say(f"forward: max |dz|/bound {r.max():.3f}, rel err {_rel(z, zr):.2e}")
+    assert np.all(np.abs(z - zr) <= Ez)
     net.close()
 
 
 def test_gradient_matches_reference(P, ctx):
+    """Loss and every gradient element within the bf16-product bounds."""
     arch = SMALL
     net = _net(P, ctx, arch)
     w = _init(arch, 3)
     net.set_params(w)
     imgs, tidx, tp = _data(arch, 5, 4, 4)
     loss, g = net.backward(imgs, tidx, tp, want_grad=True)
-    lr, gr = C.loss_and_grad(arch, w.astype(np.float64), imgs, tidx, tp.astype(np.float64))
-    _say(f"loss {loss:.6f} vs {lr:.6f}")
-    assert abs(loss - lr) < 2e-2 * max(1.0, abs(lr))
+    lr, gr, _, Eloss, Eg, _ = CB.grad_bound(arch, w.astype(np.float64), imgs, tidx, tp.astype(np.float64))
+    _say(f"loss {loss:.6f} vs {lr:.6f} (bound {Eloss:.2e})")
+    assert abs(loss - lr) <= Eloss
     off = 0
     for name, shape in arch.shapes():
         n = int(np.prod(shape))
-        e = _rel(g[off:off + n], gr[off:off + n])
-        cos = float(np.dot(g[off:off + n], gr[off:off + n]) /
-                    max(np.linalg.norm(g[off:off + n]) * np.linalg.norm(gr[off:off + n]), 1e-30))
-        _say(f"  {name}: rel err {e:.2e} cos {cos:.6f}")
-        assert e < 5e-2 and cos > 0.998, name
+        d, e = np.abs(g[off:off + n] - gr[off:off + n]), Eg[off:off + n]
+        _say(f"  {name}: max |dg|/bound {np.max(d / np.maximum(e, 1e-300)):.3f}, rel err {_rel(g[off:off + n], gr[off:off + n]):.2e}")
+        assert np.all(d <= e), name
         off += n
     net.close()
 
@@ -134,6 +138,62 @@ def test_adam_reduces_loss(P, ctx):
         net.adam(3e-3)
     _say(f"loss {first:.4f} -> {loss:.4f}")
     assert loss < 0.5 * first
+    net.close()
+
+
+def test_adam_matches_reference(P, ctx):
+    """bioem_cnn_adam against the FP64 Adam step (cnn_oracle.adam_step).
+
+    Phase 1: three steps with one gradient (backward once, adam three times):
+    the corrected moments stay g and g^2, so both sides move each weight by
+    3 lr g/(|g| + eps), checked where the reference gradient's sign is
+    certain (|g| above its bf16 bound).  Phase 2: one more step with the
+    gradient of another batch at the new parameters; where both gradients
+    have the same sign and relative bounds rho <= 10%, the step changes by at
+    most 2 rho / (1 - rho) of itself, so the library's step must match the
+    reference within that; the same check against a reference with beta1 and
+    beta2 swapped must fail somewhere (the test can tell)."""
+    arch = SMALL
+    lr, b1, b2, eps = 1e-3, 0.3, 0.99, 1e-10
+    net = _net(P, ctx, arch)
+    w0 = _init(arch, 9)
+    net.set_params(w0)
+    imgs_a, tidx_a, tp_a = _data(arch, 6, 3, 10)
+    imgs_b, tidx_b, tp_b = _data(arch, 6, 3, 11)
+    net.backward(imgs_a, tidx_a, tp_a)
+    for _ in range(3):
+        net.adam(lr, b1, b2, eps)
+    w3 = net.get_params().astype(np.float64)
+    W0 = w0.astype(np.float64)
+    _, ga, _, _, Ega, _ = CB.grad_bound(arch, W0, imgs_a, tidx_a, tp_a.astype(np.float64))
+    wr, m, v = W0, np.zeros_like(W0), np.zeros_like(W0)
+    for t in range(1, 4):
+        wr, m, v = C.adam_step(wr, ga, m, v, t, lr, b1, b2, eps)
+    sure = np.abs(ga) > Ega + 1e-4
+    fp32 = 4 * 2.0 ** -24 * (np.abs(W0) + 3 * lr)
+    _say(f"adam phase 1: {sure.sum()} of {sure.size} weights with a certain gradient sign")
+    assert sure.sum() > 0.3 * sure.size
+    np.testing.assert_array_less(np.abs(w3 - wr)[sure], (3 * lr * 1e-5 + fp32)[sure])
+    assert np.all(np.abs(w3 - W0) <= 3 * lr * (1 + 1e-5) + fp32)
+    # phase 2: a different gradient, at the new parameters
+    net.backward(imgs_b, tidx_b, tp_b)
+    net.adam(lr, b1, b2, eps)
+    w4 = net.get_params().astype(np.float64)
+    _, gb, _, _, Egb, _ = CB.grad_bound(arch, wr, imgs_b, tidx_b, tp_b.astype(np.float64))
+    w4r, _, _ = C.adam_step(wr, gb, m, v, 4, lr, b1, b2, eps)
+    rho = np.maximum(Ega / np.abs(ga), Egb / np.maximum(np.abs(gb), 1e-300))
+    sel = (np.sign(ga) == np.sign(gb)) & (rho <= 0.1) & (np.abs(gb) > 1e-6)
+    step_r = w4r - wr
+    tol = 2.5 * rho * np.abs(step_r) + lr * 1e-5 + 4 * 2.0 ** -24 * (np.abs(wr) + lr)
+    _say(f"adam phase 2: {sel.sum()} weights checked")
+    assert sel.sum() >= 50
+    np.testing.assert_array_less(np.abs((w4 - w3) - step_r)[sel], tol[sel])
+    # the check discriminates: swapped betas give other steps on these weights
+    ws, ms, vs = W0, np.zeros_like(W0), np.zeros_like(W0)
+    for t in range(1, 4):
+        ws, ms, vs = C.adam_step(ws, ga, ms, vs, t, lr, b2, b1, eps)
+    w4s, _, _ = C.adam_step(ws, gb, ms, vs, 4, lr, b2, b1, eps)
+    assert np.any(np.abs((w4s - ws) - step_r)[sel] > tol[sel])
     net.close()
 
 
