@@ -54,6 +54,7 @@ def mixed(P):
             jobs.append(dict(proj=proj, imgs=im, ctf=cls.ctf, max_shift=cls.max_shift))
             refs.append(O.logpost_oracle(imgs, wl.models[m], quats, cls.ctf, cls.pixel_A,
                                          cls.max_shift, method="fft"))
+            refs[-1].rescore = (imgs, wl.models[m], quats, cls.ctf, cls.pixel_A)
     return ctx, wl, jobs, refs
 
 
@@ -68,6 +69,13 @@ def test_persistent_batch_matches_oracle(P, mixed, prec, tol):
         assert d <= tol, j
         assert np.abs(o["best"]["logl"] - r.best_logl).max() <= tol, j
         assert np.all(o["best"]["status"] == 0)
+        # every reported grid point attains the maximum by the oracle's own
+        # likelihood there
+        imgs, model, quats, ctf, pixel = r.rescore
+        b = o["best"]
+        for i in range(len(imgs)):
+            l_at = O.loglik_at(imgs[i], model, quats[b["q"][i]], ctf[b["c"][i]], pixel, b["dx"][i], b["dy"][i])
+            assert abs(l_at - r.best_logl[i]) <= tol, (j, i, l_at, r.best_logl[i])
         assert np.abs(o["orient"][:, :NQ] - r.logp_orient[:, :NQ]).max() <= tol, j
 
 

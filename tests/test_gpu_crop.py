@@ -38,7 +38,10 @@ def ctx(P):
     return P.Context(0)
 
 
-def _check(out, r, tol=TOL):
+def _check(out, r, tol=TOL, rescore=None):
+    """log P and best points against the oracle; rescore = (imgs, model,
+    quats, ctf, pixel): every reported point must attain the maximum by the
+    oracle's own likelihood there."""
     d = np.abs(out["logp"] - r.logp)
     _say(f"  max |dlogP| = {d.max():.3e}")
     assert d.max() <= tol, d
@@ -47,6 +50,12 @@ def _check(out, r, tol=TOL):
     assert np.abs(b["logl"] - r.best_logl).max() <= tol
     same = (b["q"] == r.best_q) & (b["c"] == r.best_c) & (b["dx"] == r.best_dx) & (b["dy"] == r.best_dy)
     assert same.mean() >= 0.8, same
+    if rescore is not None:
+        imgs, model, quats, ctf, pixel = rescore
+        for i in range(len(imgs)):
+            l_at = O.loglik_at(imgs[i], model, quats[b["q"][i]], ctf[b["c"][i]], pixel, b["dx"][i], b["dy"][i],
+                               borders="crop")
+            assert abs(l_at - r.best_logl[i]) <= tol, (i, l_at, r.best_logl[i])
 
 
 @pytest.mark.parametrize("S", [0, 1, 2, 3])
@@ -60,7 +69,7 @@ def test_crop_matches_oracle_64px(P, ctx, S):
     r = O.logpost_oracle(imgs, wl.models[0], quats, ctf, cls.pixel_A, S, borders="crop")
     proj = P.project(ctx, wl.models[0], quats, cls.nx, cls.ny, cls.pixel_A)
     out = P.logpost_crop(ctx, proj, imgs, ctf, S)
-    _check(out, r)
+    _check(out, r, rescore=(imgs, wl.models[0], quats, ctf, cls.pixel_A))
     if S == 0:
         # no displacement: the same function as the wrapped Fourier form
         im = P.prepare_images(ctx, imgs)
@@ -88,7 +97,7 @@ def test_crop_ragged_box_device_memory(P, ctx):
                          device_out=True)
     torch.cuda.synchronize()
     host = {"logp": out["logp"].cpu().numpy(), "best": P.best_from_bytes(out["best"])}
-    _check(host, r)
+    _check(host, r, rescore=(imgs.astype(np.float64), wl.models[0], quats, ctf, pix))
     proj.free()
 
 
@@ -104,7 +113,7 @@ def test_crop_full_box_sample(P, ctx):
     r = O.logpost_oracle(imgs, wl.models[0], quats, ctf, cls.pixel_A, S, borders="crop")
     proj = P.project(ctx, wl.models[0], quats, cls.nx, cls.ny, cls.pixel_A)
     out = P.logpost_crop(ctx, proj, imgs, ctf, S)
-    _check(out, r)
+    _check(out, r, rescore=(imgs, wl.models[0], quats, ctf, cls.pixel_A))
     proj.free()
 
 

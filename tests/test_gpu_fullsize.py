@@ -74,6 +74,11 @@ def test_fullsize_matches_stored_oracle(P, setup, prec):
         assert abs(b["logl"][i] - r["best_logl"]) <= tol, (i, b["logl"][i], r["best_logl"])
         if b["q"][i] == r["best_q"] and b["c"][i] == r["best_c"]:
             assert (b["dx"][i], b["dy"][i]) == (r["best_dx"], r["best_dy"])
+        # the reported grid point attains the maximum by the oracle's own
+        # likelihood there (several points can be within the tolerance)
+        l_at = O.loglik_at(imgs[i], wl.models[0], cls.quats[b["q"][i]], cls.ctf[b["c"][i]], cls.pixel_A,
+                           b["dx"][i], b["dy"][i])
+        assert abs(l_at - r["best_logl"]) <= tol, (i, l_at, r["best_logl"])
         for q, v in r["orient"].items():
             assert abs(out["orient"][i, int(q)] - v) <= tol, (i, q, out["orient"][i, int(q)], v)
     # the per-orientation values and log P agree with each other at any size
