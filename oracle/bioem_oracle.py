@@ -125,6 +125,56 @@ def filtered_projection(i0: np.ndarray, table: np.ndarray) -> np.ndarray:
     return np.fft.irfft2(np.fft.rfft2(i0) * table, s=(ny, nx))
 
 
+def psf_kernel(a: float, amp: float, b: float, nx: int, ny: int, pixel: float, R: int) -> np.ndarray:
+    """The real-space PSF of Eq. (3), truncated to radius R pixels:
+    K[dy + R][dx + R] = PSF(dx, dy) where dx^2 + dy^2 <= R^2, else 0.
+
+    PSF = F^-1[CTF Env] on the box grid (the inverse of Eq. 2, with its
+    1/N_pix), the radially symmetric image that Section 3 (Imaging effects)
+    precalculates; the real-space form is meant for a PSF that is negligible
+    away from the origin, hence the truncation.  Needs R < min(nx, ny) / 2."""
+    if not 0 <= R < min(nx, ny) // 2:
+        raise ValueError(f"PSF radius {R} outside [0, min(nx, ny)/2)")
+    psf = np.fft.irfft2(ctf_envelope_table(a, amp, b, nx, ny, pixel), s=(ny, nx))
+    d = np.arange(-R, R + 1)
+    K = psf[(d % ny)[:, None], (d % nx)[None, :]]
+    K[(d[:, None] ** 2 + d[None, :] ** 2) > R * R] = 0.0
+    return K
+
+
+def psf_convolution(i0: np.ndarray, K: np.ndarray) -> np.ndarray:
+    """Eq. (5) on the box without wrap: I1(r) = sum over r' in the box of
+    I0(r') PSF(r - r'), with PSF(delta) = K[delta + R] (zero outside the
+    kernel); pixels of I0 outside the box count as zero.  Written as the sum
+    over the kernel's offsets delta of K(delta) I0(r - delta)."""
+    i0 = np.asarray(i0, dtype=np.float64)
+    ny, nx = i0.shape
+    R = K.shape[0] // 2
+    out = np.zeros((ny, nx))
+    for dy in range(-R, R + 1):
+        for dx in range(-R, R + 1):
+            w = K[dy + R, dx + R]
+            if w == 0.0:
+                continue
+            # out[y, x] += w i0[y - dy, x - dx] for 0 <= y - dy < ny, 0 <= x - dx < nx
+            y0, y1 = max(0, dy), min(ny, ny + dy)
+            x0, x1 = max(0, dx), min(nx, nx + dx)
+            if y0 < y1 and x0 < x1:
+                out[y0:y1, x0:x1] += w * i0[y0 - dy:y1 - dy, x0 - dx:x1 - dx]
+    return out
+
+
+def calculated_image(spheres: np.ndarray, q, ctf, nx: int, ny: int, pixel: float,
+                     psf_radius: Optional[int] = None) -> np.ndarray:
+    """I1 of Eq. (4) (Fourier filter, the default) or of Eq. (5) (real-space
+    convolution with the PSF truncated to ``psf_radius`` pixels)."""
+    a, amp, b = ctf
+    i0 = project_model(spheres, q, nx, ny, pixel)
+    if psf_radius is None:
+        return filtered_projection(i0, ctf_envelope_table(a, amp, b, nx, ny, pixel))
+    return psf_convolution(i0, psf_kernel(a, amp, b, nx, ny, pixel, psf_radius))
+
+
 # ---------------------------------------------------------------------------
 # Precomputed sums and the cross-correlation (Section 3; Center displacement)
 # ---------------------------------------------------------------------------
@@ -255,18 +305,16 @@ def log_likelihood(X, A: float, B: float, n: int):
 
 
 def loglik_at(image: np.ndarray, spheres: np.ndarray, q, ctf, pixel: float, dx: int, dy: int,
-              borders: str = "wrap") -> float:
+              borders: str = "wrap", psf_radius: Optional[int] = None) -> float:
     """l(q, c, d) of one image at one grid point (Eq. likeli integrated, as
     ``log_likelihood``), with the correlation at d summed directly:
     X = sum_r (I_o(r) - mean) I1_d(r), where I1_d(r) = I1((r + d) mod box)
     for the Fourier variant and I1(r + d) inside the box, 0 outside, with
     ``borders="crop"`` (then B is taken of I1_d).  -inf where nothing moved
-    in (B = 0)."""
+    in (B = 0).  ``psf_radius`` takes I1 from Eq. (5) (``calculated_image``)."""
     img = np.asarray(image, dtype=np.float64)
     ny, nx = img.shape
-    a, amp, b = ctf
-    i1 = filtered_projection(project_model(spheres, q, nx, ny, pixel),
-                             ctf_envelope_table(a, amp, b, nx, ny, pixel))
+    i1 = calculated_image(spheres, q, ctf, nx, ny, pixel, psf_radius)
     A = image_moments(img)[2]
     dx, dy = int(dx), int(dy)
     if borders == "wrap":
@@ -348,7 +396,8 @@ class OracleResult:
 
 def logpost_oracle(images: np.ndarray, spheres: np.ndarray, quats: np.ndarray,
                    ctfs: np.ndarray, pixel: float, S: int, method: str = "direct",
-                   q_subset: Optional[Sequence[int]] = None, borders: str = "wrap") -> OracleResult:
+                   q_subset: Optional[Sequence[int]] = None, borders: str = "wrap",
+                   psf_radius: Optional[int] = None) -> OracleResult:
     """log P_{m,omega} for every image over the orientation x CTF x shift grid.
 
     P is the integral of Eq. (Pmom) with mu, N and lambda integrated
@@ -362,6 +411,9 @@ def logpost_oracle(images: np.ndarray, spheres: np.ndarray, quats: np.ndarray,
     ``q_subset`` evaluates only those orientations (the prior keeps Nq).
     ``borders="crop"`` takes the real-space variant with cropping
     (``correlation_cropped``: B depends on d) instead of the wrap.
+    ``psf_radius`` builds each calculated image by the real-space PSF
+    convolution of Eq. (5) (``psf_kernel``, ``psf_convolution``) instead of
+    the Fourier filter of Eq. (4).
     """
     imgs = np.asarray(images, dtype=np.float64)
     ni, ny, nx = imgs.shape
@@ -385,7 +437,10 @@ def logpost_oracle(images: np.ndarray, spheres: np.ndarray, quats: np.ndarray,
         i0 = project_model(spheres, quats[q], nx, ny, pixel)
         per_c = np.empty((ni, nc, 2 * S + 1, 2 * S + 1))
         for c in range(nc):
-            i1 = filtered_projection(i0, tables[c])
+            if psf_radius is None:
+                i1 = filtered_projection(i0, tables[c])
+            else:
+                i1 = psf_convolution(i0, psf_kernel(*ctfs[c], nx, ny, pixel, psf_radius))
             if borders == "crop":
                 X, Bd = correlation_cropped(imgs, i1, S)
                 for i in range(ni):
