@@ -383,6 +383,28 @@ bioem_status bioem_logpost_crop(bioem_ctx* ctx, const bioem_proj* proj, const fl
                                 int32_t in_mem, const double* ctf, int32_t nc, int32_t max_shift, double* logp,
                                 bioem_best* best, int32_t out_mem);
 
+/* bioem_logpost_crop with the calculated images built by the real-space
+ * convolution of Eq. (5) instead of the Fourier filter of Eq. (4) (Section 3,
+ * Imaging effects: the real-space form pays off when the PSF is negligible
+ * away from the origin).  For each CTF set the PSF is the inverse transform
+ * of CTF x Env on the box grid (Eq. 3, FP64), truncated to the disc
+ * dx^2 + dy^2 <= psf_radius^2; each ideal projection I0 (FP64) is convolved
+ * with it on the box without wrap (pixels outside the box count as zero),
+ *   I1(x, y) = sum_{dx,dy} PSF(dx, dy) I0(x - dx, y - dy),
+ * in FP64 and stored as FP32; the cropped displacement sum and everything
+ * after it are those of bioem_logpost_crop.  Near the borders the result
+ * differs from the Fourier filter, which wraps; away from them it agrees to
+ * the part of the PSF beyond the radius.
+ * Arguments as bioem_logpost_crop, plus psf_radius in [0, min(nx, ny)/2).
+ * EINVAL: as bioem_logpost_crop, or psf_radius outside that range.
+ * EUNSUPPORTED: as bioem_logpost_crop, or psf_radius > 32.
+ * Device memory used beyond bioem_logpost_crop's: nc PSF images (8 B per
+ * pixel, with their transform scratch) and nc (2 psf_radius + 1)^2 kernel
+ * values. */
+bioem_status bioem_logpost_crop_psf(bioem_ctx* ctx, const bioem_proj* proj, const float* imgs, int32_t ni,
+                                    int32_t in_mem, const double* ctf, int32_t nc, int32_t max_shift,
+                                    int32_t psf_radius, double* logp, bioem_best* best, int32_t out_mem);
+
 /* Posterior of a model ensemble, Eq. (pb2) of Section 2: models m = 0..nm-1
  * with relative weights w_m (w_m >= 0, summing to 1 within 1e-9) and the
  * per-image log posteriors logp[m][i] that bioem_logpost returns for each

@@ -111,6 +111,7 @@ SIGNATURES = [
     ("bioem_topk", _I, [_P, _P, _I, _I, _I, _I, _P, _P, _I]),
     ("bioem_ensemble", _I, [_P, _P, _I, _I, _I, _P, _P, _P, _I]),
     ("bioem_logpost_crop", _I, [_P, _P, _P, _I, _I, _P, _I, _I, _P, _P, _I]),
+    ("bioem_logpost_crop_psf", _I, [_P, _P, _P, _I, _I, _P, _I, _I, _I, _P, _P, _I]),
     ("bioem_cnn_input", _I, [_P, _P, _I, _I, _I, _I, _P, _I]),
 ]
 
@@ -407,10 +408,13 @@ def topk(ctx: Context, z, K: int, device_out: bool = False):
     return idx, mass
 
 
-def logpost_crop(ctx: Context, proj: Projections, images, ctf, max_shift: int, device_out: bool = False):
+def logpost_crop(ctx: Context, proj: Projections, images, ctf, max_shift: int, device_out: bool = False,
+                 psf_radius=None):
     """Log posterior per image with the real-space, border-cropping form of
     the displacement sum (direct correlation, max_shift <= 3); images are the
-    raw pixels [ni][ny][nx] (numpy or CUDA tensor)."""
+    raw pixels [ni][ny][nx] (numpy or CUDA tensor).  With ``psf_radius`` the
+    calculated images come from the real-space PSF convolution of Eq. (5)
+    (bioem_logpost_crop_psf)."""
     ip, im, keep = _arg(images, np.float32)
     if keep.ndim != 3 or tuple(keep.shape[1:]) != (proj.ny, proj.nx):
         raise ValueError(f"images must be [ni][{proj.ny}][{proj.nx}]")
@@ -419,18 +423,23 @@ def logpost_crop(ctx: Context, proj: Projections, images, ctf, max_shift: int, d
     if cm != im:
         raise ValueError("images and ctf must both be host arrays or both device tensors")
     nc = int(ck.shape[0])
+
+    def call(lp, bp, mem):
+        if psf_radius is None:
+            return ctx._lib.bioem_logpost_crop(ctx.h, proj.h, ip, ni, im, cp, nc, int(max_shift), lp, bp, mem)
+        return ctx._lib.bioem_logpost_crop_psf(ctx.h, proj.h, ip, ni, im, cp, nc, int(max_shift), int(psf_radius),
+                                               lp, bp, mem)
+
     if device_out:
         torch = _torch()
         dev = torch.device("cuda", ctx.device)
         logp = torch.empty(ni, dtype=torch.float64, device=dev)
         best = torch.empty(ni * BEST_DTYPE.itemsize, dtype=torch.uint8, device=dev)
-        ctx.check(ctx._lib.bioem_logpost_crop(ctx.h, proj.h, ip, ni, im, cp, nc, int(max_shift), logp.data_ptr(),
-                                              best.data_ptr(), MEM_DEVICE))
+        ctx.check(call(logp.data_ptr(), best.data_ptr(), MEM_DEVICE))
         return {"logp": logp, "best": best}
     logp = np.empty(ni, np.float64)
     best = np.empty(ni, BEST_DTYPE)
-    ctx.check(ctx._lib.bioem_logpost_crop(ctx.h, proj.h, ip, ni, im, cp, nc, int(max_shift), logp.ctypes.data,
-                                          best.ctypes.data, MEM_HOST))
+    ctx.check(call(logp.ctypes.data, best.ctypes.data, MEM_HOST))
     return {"logp": logp, "best": best}
 
 

@@ -868,10 +868,15 @@ bioem_status bioem_project_euler(bioem_ctx* ctx, const double* spheres, int32_t 
   return bioem_project(ctx, dsp.as<double>(), ns, dq.as<double>(), nq, nx, ny, pixel_A, BIOEM_MEM_DEVICE, out);
 }
 
-bioem_status bioem_logpost_crop(bioem_ctx* ctx, const bioem_proj* proj, const float* imgs, int32_t ni,
-                                int32_t in_mem, const double* ctf, int32_t nc, int32_t max_shift, double* logp,
-                                bioem_best* best, int32_t out_mem) {
-  if (!ctx) return BIOEM_EINVAL;
+}  // extern "C"
+
+namespace {
+
+// The cropping posterior with calculated images from the Fourier filter of
+// Eq. (4) (psf_radius < 0) or the real-space PSF convolution of Eq. (5).
+bioem_status crop_impl(bioem_ctx* ctx, const bioem_proj* proj, const float* imgs, int32_t ni, int32_t in_mem,
+                       const double* ctf, int32_t nc, int32_t max_shift, int32_t psf_radius, double* logp,
+                       bioem_best* best, int32_t out_mem) {
   if (!proj || !imgs || !ctf || !logp || !best || ni < 1 || nc < 1 || !valid_mem(in_mem) || !valid_mem(out_mem))
     return fail(ctx, BIOEM_EINVAL, "bioem_logpost_crop: bad argument");
   const int nx = proj->nx, ny = proj->ny, nq = proj->n, S = max_shift;
@@ -883,6 +888,11 @@ bioem_status bioem_logpost_crop(bioem_ctx* ctx, const bioem_proj* proj, const fl
                 "%zu bytes of LDS at this box)", kCropMaxShift, crop_smem_bytes(nx, S));
   if ((size_t)nq * nc > (size_t)INT32_MAX / 2)
     return fail(ctx, BIOEM_EINVAL, "bioem_logpost_crop: too many orientation x CTF pairs");
+  const int R = psf_radius;
+  if (R >= 0 && 2 * R >= std::min(nx, ny))
+    return fail(ctx, BIOEM_EINVAL, "bioem_logpost_crop_psf: psf_radius %d outside [0, min(nx, ny)/2)", R);
+  if (R > kPsfMaxRadius)
+    return fail(ctx, BIOEM_EUNSUPPORTED, "bioem_logpost_crop_psf: psf_radius %d above %d", R, kPsfMaxRadius);
   HIP_OR_FAIL(ctx, hipSetDevice(ctx->device));
   hipStream_t s = ctx->stream;
   const int np = nq * nc, W = (2 * S + 1) * (2 * S + 1), mh = nx / 2 + 1;
@@ -910,7 +920,30 @@ bioem_status bioem_logpost_crop(bioem_ctx* ctx, const bioem_proj* proj, const fl
   HIP_OR_FAIL(ctx, s64.alloc((size_t)chunk * len * 16));
   HIP_OR_FAIL(ctx, cols.alloc((size_t)chunk * ny * mh * 16));
   HIP_OR_FAIL(ctx, i1.alloc((size_t)chunk * npix * 8));
-  for (int c = 0; c < nc; ++c) {
+  if (R >= 0) {
+    // Eq. (5): each CTF set's PSF, truncated to the disc of radius R, then
+    // every ideal image convolved with it on the box
+    const size_t w2 = (size_t)(2 * R + 1) * (2 * R + 1);
+    DevIn dctf;
+    DevMem pspec, pcols, ppsf, K;
+    HIP_OR_FAIL(ctx, dctf.set(hc.data(), hc.size() * 8, BIOEM_MEM_HOST, s));
+    HIP_OR_FAIL(ctx, pspec.alloc((size_t)nc * len * 16));
+    HIP_OR_FAIL(ctx, pcols.alloc((size_t)nc * ny * mh * 16));
+    HIP_OR_FAIL(ctx, ppsf.alloc((size_t)nc * npix * 8));
+    HIP_OR_FAIL(ctx, K.alloc(sizeof(double) * nc * w2));
+    HIP_OR_FAIL(ctx, launch_psf_kernels(s, dctf.as<double>(), nc, nx, ny, proj->pixel, R, pspec.as<double2>(),
+                                        pcols.as<double2>(), ppsf.as<double>(), K.as<double>()));
+    for (int q0 = 0; q0 < nq; q0 += chunk) {
+      const int cn = std::min(chunk, nq - q0);
+      HIP_OR_FAIL(ctx, launch_ideal(s, proj->spec + slen * q0, proj->expo + q0, cn, nx, ny, s64.as<double2>(),
+                                    cols.as<double2>(), i1.as<double>()));
+      for (int c = 0; c < nc; ++c)
+        HIP_OR_FAIL(ctx, launch_psf_conv(s, i1.as<double>(), cn, nx, ny, K.as<double>() + w2 * c, R,
+                                         P.as<float>() + npix * ((size_t)c * nq + q0)));
+    }
+    HIP_OR_FAIL(ctx, hipStreamSynchronize(s));   // the PSF buffers are freed on leaving this block
+  }
+  for (int c = 0; c < nc && R < 0; ++c) {
     for (int q = 0; q < nq; ++q)
       for (int k = 0; k < 3; ++k) rep[3 * (size_t)q + k] = hc[3 * (size_t)c + k];
     HIP_OR_FAIL(ctx, hipMemcpyAsync(crep.p, rep.data(), rep.size() * 8, hipMemcpyHostToDevice, s));
@@ -954,6 +987,25 @@ bioem_status bioem_logpost_crop(bioem_ctx* ctx, const bioem_proj* proj, const fl
   }
   HIP_OR_FAIL(ctx, hipStreamSynchronize(s));
   return BIOEM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+bioem_status bioem_logpost_crop(bioem_ctx* ctx, const bioem_proj* proj, const float* imgs, int32_t ni,
+                                int32_t in_mem, const double* ctf, int32_t nc, int32_t max_shift, double* logp,
+                                bioem_best* best, int32_t out_mem) {
+  if (!ctx) return BIOEM_EINVAL;
+  return crop_impl(ctx, proj, imgs, ni, in_mem, ctf, nc, max_shift, -1, logp, best, out_mem);
+}
+
+bioem_status bioem_logpost_crop_psf(bioem_ctx* ctx, const bioem_proj* proj, const float* imgs, int32_t ni,
+                                    int32_t in_mem, const double* ctf, int32_t nc, int32_t max_shift,
+                                    int32_t psf_radius, double* logp, bioem_best* best, int32_t out_mem) {
+  if (!ctx) return BIOEM_EINVAL;
+  if (psf_radius < 0) return fail(ctx, BIOEM_EINVAL, "bioem_logpost_crop_psf: psf_radius %d < 0", psf_radius);
+  return crop_impl(ctx, proj, imgs, ni, in_mem, ctf, nc, max_shift, psf_radius, logp, best, out_mem);
 }
 
 bioem_status bioem_ensemble(bioem_ctx* ctx, const double* logp, int32_t nm, int32_t ni, int32_t in_mem,

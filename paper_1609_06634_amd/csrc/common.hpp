@@ -100,6 +100,18 @@ hipError_t launch_render(hipStream_t s, const float2* spec, const int32_t* expo,
                          const double* norm_offset, const float* noise, double snr,
                          double2* spec64, double2* cols_scratch, double* i1, float* out);
 
+// Ideal images I0 (no CTF) in real space, FP64: i0 [n][ny][nx].
+hipError_t launch_ideal(hipStream_t s, const float2* spec, const int32_t* expo, int n, int nx, int ny,
+                        double2* spec64, double2* cols_scratch, double* i0);
+// Real-space PSFs of nc CTF sets (Eq. 3) truncated to the disc of radius R:
+// K [nc][2R+1][2R+1] (scratch spec64 / cols [nc][nx/2+1][ny], psf [nc][ny][nx]).
+constexpr int kPsfMaxRadius = 32;
+hipError_t launch_psf_kernels(hipStream_t s, const double* ctf, int nc, int nx, int ny, double pixel, int R,
+                              double2* spec64, double2* cols_scratch, double* psf, double* K);
+// Eq. (5) on the box without wrap: out [n][ny][nx] float = I0 [n] convolved with K.
+hipError_t launch_psf_conv(hipStream_t s, const double* i0, int n, int nx, int ny, const double* K, int R,
+                           float* out);
+
 // Centred circular autocorrelation of mean-free images (lag 0 zeroed), the
 // proposal network's shift-invariant input: imgs [n][ny][nx] float ->
 // out [n][ny][nx] float; scratch rows/spec/cols [n][nx/2+1][ny] double2,

@@ -346,7 +346,8 @@ __global__ __launch_bounds__(256) void k_render_filter(const float2* __restrict_
   const int e = blockIdx.x * 256 + threadIdx.x;
   if (e >= len) return;
   const int m = e / ny, l = e - m * ny;
-  const double t = ctf_env(ctf[3 * item], ctf[3 * item + 1], ctf[3 * item + 2], m, l, nx, ny, pixel);
+  // no CTF table: the ideal image I0 itself
+  const double t = ctf ? ctf_env(ctf[3 * item], ctf[3 * item + 1], ctf[3 * item + 2], m, l, nx, ny, pixel) : 1.0;
   const float2 v = spec[item * (size_t)mh * spec_ld(ny) + (size_t)m * spec_ld(ny) + l];
   const double sc = ldexp(1.0, expo[item]) * t;
   out[item * len + e] = make_double2(v.x * sc, v.y * sc);
@@ -401,6 +402,60 @@ __global__ __launch_bounds__(128) void k_icrdft_rows(const double2* __restrict__
     }
     i1[r * nx + j] = acc * inv_n;
   }
+}
+
+// Real-space PSF of Eq. (3) for each CTF set c: its half spectrum is the real
+// CTF x Env table, so the PSF image is the inverse transform of (T, 0).
+__global__ __launch_bounds__(256) void k_psf_spec(const double* __restrict__ ctf, int nx, int ny, double pixel,
+                                                  double2* __restrict__ out) {
+  const int mh = nx / 2 + 1;
+  const size_t item = blockIdx.y;
+  const int len = mh * ny;
+  const int e = blockIdx.x * 256 + threadIdx.x;
+  if (e >= len) return;
+  const int m = e / ny, l = e - m * ny;
+  out[item * len + e] =
+      make_double2(ctf_env(ctf[3 * item], ctf[3 * item + 1], ctf[3 * item + 2], m, l, nx, ny, pixel), 0.0);
+}
+
+// The PSF truncated to the disc of radius R: K[c][dy + R][dx + R] =
+// psf[c][dy mod ny][dx mod nx] where dx^2 + dy^2 <= R^2, else 0.
+__global__ __launch_bounds__(256) void k_psf_window(const double* __restrict__ psf, int nx, int ny, int R,
+                                                    double* __restrict__ K) {
+  const int w = 2 * R + 1;
+  const size_t c = blockIdx.y;
+  const int e = blockIdx.x * 256 + threadIdx.x;
+  if (e >= w * w) return;
+  const int dy = e / w - R, dx = e % w - R;
+  K[c * w * w + e] = dx * dx + dy * dy <= R * R
+                         ? psf[c * (size_t)nx * ny + (size_t)((dy + ny) % ny) * nx + (dx + nx) % nx]
+                         : 0.0;
+}
+
+// Eq. (5) on the box without wrap, for n ideal images and one kernel:
+//   out[i][y][x] = sum_{dy,dx} K[dy + R][dx + R] I0[i][y - dy][x - dx]
+// over the offsets that stay in the box (FP64 products and sum, FP32 store).
+// grid: (ceil(npix / 256), n); the kernel sits in LDS ((2R+1)^2 doubles).
+__global__ __launch_bounds__(256) void k_psf_conv(const double* __restrict__ i0, int nx, int ny,
+                                                  const double* __restrict__ K, int R, float* __restrict__ out) {
+  extern __shared__ double ks[];
+  const int w = 2 * R + 1;
+  for (int e = threadIdx.x; e < w * w; e += 256) ks[e] = K[e];
+  __syncthreads();
+  const int npix = nx * ny;
+  const int p = blockIdx.x * 256 + threadIdx.x;
+  if (p >= npix) return;
+  const int y = p / nx, x = p - y * nx;
+  const double* src = i0 + (size_t)blockIdx.y * npix;
+  const int dy0 = max(-R, y - ny + 1), dy1 = min(R, y);     // 0 <= y - dy < ny
+  const int dx0 = max(-R, x - nx + 1), dx1 = min(R, x);
+  double acc = 0.0;
+  for (int dy = dy0; dy <= dy1; ++dy) {
+    const double* row = src + (size_t)(y - dy) * nx + x;
+    const double* kr = ks + (dy + R) * w + R;
+    for (int dx = dx0; dx <= dx1; ++dx) acc = fma(kr[dx], row[-dx], acc);
+  }
+  out[(size_t)blockIdx.y * npix + p] = (float)acc;
 }
 
 // Synthetic map, last step: shift, scale, offset and noise at the given SNR.
@@ -587,6 +642,34 @@ hipError_t launch_render(hipStream_t s, const float2* spec, const int32_t* expo,
   hipLaunchKernelGGL(k_icrdft_rows, dim3(n * ny), dim3(128), 0, s, cols_scratch, nx, ny, i1);
   hipLaunchKernelGGL(k_render_finish, dim3(n), dim3(256), 0, s, i1, nx, ny, shifts, norm_offset,
                      noise, snr, out);
+  return last();
+}
+
+hipError_t launch_ideal(hipStream_t s, const float2* spec, const int32_t* expo, int n, int nx, int ny,
+                        double2* spec64, double2* cols_scratch, double* i0) {
+  const int mh = nx / 2 + 1, len = mh * ny;
+  hipLaunchKernelGGL(k_render_filter, dim3((len + 255) / 256, n), dim3(256), 0, s, spec, expo, nx, ny, 1.0,
+                     (const double*)nullptr, spec64);
+  hipLaunchKernelGGL(k_icdft_cols, dim3(n * mh), dim3(128), 0, s, spec64, nx, ny, cols_scratch);
+  hipLaunchKernelGGL(k_icrdft_rows, dim3(n * ny), dim3(128), 0, s, cols_scratch, nx, ny, i0);
+  return last();
+}
+
+hipError_t launch_psf_kernels(hipStream_t s, const double* ctf, int nc, int nx, int ny, double pixel, int R,
+                              double2* spec64, double2* cols_scratch, double* psf, double* K) {
+  const int mh = nx / 2 + 1, len = mh * ny, w = 2 * R + 1;
+  hipLaunchKernelGGL(k_psf_spec, dim3((len + 255) / 256, nc), dim3(256), 0, s, ctf, nx, ny, pixel, spec64);
+  hipLaunchKernelGGL(k_icdft_cols, dim3(nc * mh), dim3(128), 0, s, spec64, nx, ny, cols_scratch);
+  hipLaunchKernelGGL(k_icrdft_rows, dim3(nc * ny), dim3(128), 0, s, cols_scratch, nx, ny, psf);
+  hipLaunchKernelGGL(k_psf_window, dim3((w * w + 255) / 256, nc), dim3(256), 0, s, psf, nx, ny, R, K);
+  return last();
+}
+
+hipError_t launch_psf_conv(hipStream_t s, const double* i0, int n, int nx, int ny, const double* K, int R,
+                           float* out) {
+  const int w = 2 * R + 1;
+  hipLaunchKernelGGL(k_psf_conv, dim3((nx * ny + 255) / 256, n), dim3(256), sizeof(double) * w * w, s, i0, nx,
+                     ny, K, R, out);
   return last();
 }
 
