@@ -26,7 +26,7 @@ closed-form integral itself.
 library correlation; it is likewise test infrastructure only.
 """
 from .bioem_oracle import (  # noqa: F401
-    quat_to_matrix, euler_to_matrix, project_model, ctf_envelope_table, filtered_projection,
+    quat_to_matrix, euler_to_matrix, matrix_to_quat, euler_to_quat, project_model, ctf_envelope_table, filtered_projection,
     image_moments, projection_norm, correlation_direct, correlation_fft, correlation_cropped,
     log_likelihood, loglik_at, logsumexp_exact, logpost_oracle, OracleResult, ensemble_logpost,
     render_image, render_images, signed_freq, psf_kernel, psf_convolution, calculated_image,

@@ -65,6 +65,36 @@ def euler_to_matrix(phi: float, theta: float, psi: float) -> np.ndarray:
     return rz(phi) @ ry(theta) @ rz(psi)
 
 
+def matrix_to_quat(Rm: np.ndarray) -> np.ndarray:
+    """Unit quaternion (w, x, y, z), w >= 0, of a rotation matrix (the inverse
+    of ``quat_to_matrix``): from the matrix's largest diagonal combination,
+    which keeps the square root away from zero."""
+    m = np.asarray(Rm, dtype=np.float64)
+    t = np.trace(m)
+    cand = [t, m[0, 0], m[1, 1], m[2, 2]]
+    k = int(np.argmax(cand))
+    if k == 0:
+        r = math.sqrt(1.0 + t) * 2.0
+        q = [0.25 * r, (m[2, 1] - m[1, 2]) / r, (m[0, 2] - m[2, 0]) / r, (m[1, 0] - m[0, 1]) / r]
+    elif k == 1:
+        r = math.sqrt(1.0 + m[0, 0] - m[1, 1] - m[2, 2]) * 2.0
+        q = [(m[2, 1] - m[1, 2]) / r, 0.25 * r, (m[0, 1] + m[1, 0]) / r, (m[0, 2] + m[2, 0]) / r]
+    elif k == 2:
+        r = math.sqrt(1.0 + m[1, 1] - m[0, 0] - m[2, 2]) * 2.0
+        q = [(m[0, 2] - m[2, 0]) / r, (m[0, 1] + m[1, 0]) / r, 0.25 * r, (m[1, 2] + m[2, 1]) / r]
+    else:
+        r = math.sqrt(1.0 + m[2, 2] - m[0, 0] - m[1, 1]) * 2.0
+        q = [(m[1, 0] - m[0, 1]) / r, (m[0, 2] + m[2, 0]) / r, (m[1, 2] + m[2, 1]) / r, 0.25 * r]
+    q = np.array(q)
+    q /= np.linalg.norm(q)
+    return q if q[0] >= 0 else -q
+
+
+def euler_to_quat(phi: float, theta: float, psi: float) -> np.ndarray:
+    """Unit quaternion of z-y-z Euler angles (``euler_to_matrix``)."""
+    return matrix_to_quat(euler_to_matrix(phi, theta, psi))
+
+
 def _pixel_integrals(centres: np.ndarray, pos: np.ndarray, sigma: np.ndarray,
                      pixel: float) -> np.ndarray:
     """[n_spheres][n_pixels] integral of a unit 1-D Gaussian over each pixel."""

@@ -71,3 +71,39 @@ def test_euler_arguments(P, ctx):
         P.project_euler(ctx, wl.models[0], np.array([[0.0, np.nan, 0.0]]), cls.nx, cls.ny, cls.pixel_A)
     with pytest.raises(ValueError):
         P.project_euler(ctx, wl.models[0], np.zeros((3, 4)), cls.nx, cls.ny, cls.pixel_A)
+
+
+@pytest.mark.parametrize("prec", ["f32", "split_f16"])
+def test_symmetry_restricted_set(P, ctx, prec):
+    """A C_4-symmetric model scored over a symmetry-restricted Euler set
+    (psi in [0, pi/2)) and over its four-fold expansion: log P agrees with
+    the oracle on the restricted set, equals the full set's, and the
+    restricted orientations scored as candidates under the full set's prior
+    give exactly ln 4 less."""
+    from workloads import expand_symmetry, symmetric_model, symmetry_restricted_euler
+    n = 4
+    rng = np.random.default_rng([160906634, 98])
+    sph = symmetric_model(rng, 40, n, 40.0, 2.0)
+    er = symmetry_restricted_euler(rng, 24, n)
+    ef = expand_symmetry(er, n)
+    wl = make_workload(1, n_images=5)
+    cls = wl.classes[0]
+    imgs = np.array([O.render_image(sph, O.euler_to_quat(*rng.uniform(0, 6, 3)), cls.img_ctf[i], cls.img_shift[i],
+                                    cls.nx, cls.ny, cls.pixel_A, 1.0, 0.0, rng.standard_normal((cls.ny, cls.nx)),
+                                    0.5) for i in range(5)], dtype=np.float32)
+    _say(f"symmetry {prec}: C_{n} model, 5 images x {len(er)} restricted / {len(ef)} full orientations")
+    qr = np.array([O.euler_to_quat(*e) for e in er])
+    r = O.logpost_oracle(imgs.astype(np.float64), sph, qr, cls.ctf, cls.pixel_A, cls.max_shift, method="fft")
+    pr = P.project_euler(ctx, sph, er, cls.nx, cls.ny, cls.pixel_A)
+    pf = P.project_euler(ctx, sph, ef, cls.nx, cls.ny, cls.pixel_A)
+    im = P.prepare_images(ctx, imgs)
+    o_r = P.logpost(ctx, pr, im, cls.ctf, cls.max_shift, prec=prec)
+    o_f = P.logpost(ctx, pf, im, cls.ctf, cls.max_shift, prec=prec)
+    cand = np.tile(np.arange(len(er), dtype=np.int32), (5, 1))
+    o_s = P.logpost(ctx, pf, im, cls.ctf, cls.max_shift, prec=prec, cand_q=cand)
+    d_or = np.abs(o_r["logp"] - r.logp).max()
+    d_rf = np.abs(o_r["logp"] - o_f["logp"]).max()
+    d_sf = np.abs(o_s["logp"] - (o_f["logp"] - np.log(n))).max()
+    _say(f"  |restricted - oracle| {d_or:.2e}, |restricted - full| {d_rf:.2e}, |subset - (full - ln 4)| {d_sf:.2e}")
+    assert d_or <= 0.01 and d_rf <= 0.01 and d_sf <= 0.01
+    assert o_r["best"]["q"].max() < len(er)

@@ -13,5 +13,6 @@ only invariance tests use.
 """
 from .configs import (  # noqa: F401
     Workload, SizeClass, make_workload, CONFIGS, electron_wavelength_A,
-    ctf_abA_from_physical, shoemake_quaternions, proposal_training_images,
+    ctf_abA_from_physical, shoemake_quaternions, proposal_training_images, symmetric_model,
+    symmetry_restricted_euler, expand_symmetry,
 )

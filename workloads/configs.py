@@ -61,6 +61,38 @@ def shoemake_quaternions(rng: np.random.Generator, n: int) -> np.ndarray:
     return q
 
 
+def symmetric_model(rng: np.random.Generator, n_per_copy: int, n_fold: int, radius: float,
+                    sigma: float) -> np.ndarray:
+    """A C_n-symmetric sphere model [n_fold * n_per_copy][5]: spheres drawn
+    uniformly in a ball, then copied by the rotations about the z axis by
+    2 pi k / n_fold (the model's symmetry axis), unit weights."""
+    base = _ball_spheres(rng, n_per_copy, radius, sigma)
+    out = []
+    for k in range(n_fold):
+        a = 2.0 * np.pi * k / n_fold
+        c, s_ = np.cos(a), np.sin(a)
+        cp = base.copy()
+        cp[:, 0] = c * base[:, 0] - s_ * base[:, 1]
+        cp[:, 1] = s_ * base[:, 0] + c * base[:, 1]
+        out.append(cp)
+    return np.concatenate(out)
+
+
+def symmetry_restricted_euler(rng: np.random.Generator, n: int, n_fold: int) -> np.ndarray:
+    """n orientations as z-y-z Euler angles (phi, theta, psi) restricted for a
+    C_n model: psi, the first turn about the model's own z axis, in
+    [0, 2 pi / n_fold); phi uniform in [0, 2 pi), cos(theta) uniform."""
+    u = rng.random((n, 3))
+    return np.stack([2.0 * np.pi * u[:, 0], np.arccos(1.0 - 2.0 * u[:, 1]), 2.0 * np.pi * u[:, 2] / n_fold], axis=1)
+
+
+def expand_symmetry(euler: np.ndarray, n_fold: int) -> np.ndarray:
+    """The full set of a restricted one: each orientation with psi + 2 pi k /
+    n_fold for k = 0..n_fold-1, copies of the restricted set in k order."""
+    e = np.asarray(euler, np.float64)
+    return np.concatenate([e + np.array([0.0, 0.0, 2.0 * np.pi * k / n_fold]) for k in range(n_fold)])
+
+
 def _ball_spheres(rng: np.random.Generator, n: int, radius: float, sigma: float) -> np.ndarray:
     """[n][5] spheres (x, y, z, sigma, weight) uniform in a ball, unit weight."""
     d = rng.standard_normal((n, 3))
