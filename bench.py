@@ -180,15 +180,22 @@ def main() -> int:
                     help="images x orientations x CTF sets for the oracle's FFT form")
     ap.add_argument("--cpu-sample-direct", default="2x8x2",
                     help="the same for the oracle's direct correlation")
-    ap.add_argument("--workload", default="paper224", choices=["paper224", "mixed", "proposal", "crossover"],
+    ap.add_argument("--workload", default="paper224", choices=["paper224", "mixed", "smalljobs", "proposal",
+                                                                   "crossover"],
                     help="paper224: 224^2, 1000 images x 4608 orientations x 8 CTF sets (default); "
                          "mixed: 96/128/180/224 px classes x two models in one persistent launch; "
                          "proposal: 128^2 x 36,864 orientations with the learned top-K proposal; "
                          "crossover: real-space (cropping) against Fourier forms for S = 0..3 at 224^2")
     ap.add_argument("--train-images", type=int, default=100000)
-    ap.add_argument("--epochs", type=int, default=4)
+    ap.add_argument("--epochs", type=int, default=60, help="proposal: at most this many epochs")
+    ap.add_argument("--plateau", type=float, default=0.003,
+                    help="proposal: stop when the loss has not improved by this fraction in 3 epochs")
     ap.add_argument("--topk", type=int, default=256)
     ap.add_argument("--tau", type=float, default=0.5)
+    ap.add_argument("--channels", default="32,64,128,128", help="proposal: convolution channels")
+    ap.add_argument("--snr", type=float, default=None, help="proposal: SNR of training and held-out images")
+    ap.add_argument("--job-images", type=int, default=16, help="smalljobs: images per job")
+    ap.add_argument("--job-orientations", type=int, default=288, help="smalljobs: orientations per job")
     ap.add_argument("--plain-images", type=int, default=8,
                     help="proposal workload: images scored by the plain FP32 form for comparison")
     ap.add_argument("--no-autotune", action="store_true",
@@ -223,6 +230,8 @@ def main() -> int:
     ctx = P.Context(0)
     if args.workload == "mixed":
         return run_mixed(args, P, ctx, torch, dev)
+    if args.workload == "smalljobs":
+        return run_smalljobs(args, P, ctx, torch, dev)
     if args.workload == "proposal":
         return run_proposal(args, P, ctx, torch, dev)
     if args.workload == "crossover":
@@ -526,6 +535,74 @@ def run_mixed(args, P, ctx, torch, dev) -> int:
     return 0
 
 
+def run_smalljobs(args, P, ctx, torch, dev) -> int:
+    """Many small, uneven jobs in one call: for each of the mixed workload's
+    four box sizes and two models, 6 jobs of 16 images over 288 orientations
+    by default (--job-images, --job-orientations; the class's own CTF grid
+    and window): 48 jobs, none of which fills the GPU alone.  Timed: bioem_logpost_batch in one persistent launch against
+    one launch per job (inputs and projections prepared beforehand)."""
+    import numpy as np
+    from workloads import make_workload
+    per, nq_job, reps = args.job_images, args.job_orientations, 6
+    log(f"generating {len(range(reps)) * 8} small jobs ({per} images x {nq_job} orientations each)")
+    wl = make_workload(4, n_images=per * reps)
+    models = [torch.from_numpy(m).to(dev) for m in wl.models]
+    jobs, handles = [], []
+    evals = 0
+    for cls in wl.classes:
+        pr_img = P.project(ctx, models[0], torch.from_numpy(cls.img_quat).to(dev), cls.nx, cls.ny, cls.pixel_A)
+        imgs = P.render(ctx, pr_img, torch.from_numpy(cls.img_ctf).to(dev), torch.from_numpy(cls.img_shift).to(dev),
+                        noise=torch.from_numpy(cls.noise(0, per * reps)).to(dev), snr=cls.snr, device_out=True)
+        pr_img.free()
+        ctf = torch.from_numpy(cls.ctf).to(dev)
+        for r in range(reps):
+            im = P.prepare_images(ctx, imgs[r * per:(r + 1) * per].contiguous())
+            handles.append(im)
+            for m in range(2):
+                q = torch.from_numpy(cls.quats[(r * nq_job) % len(cls.quats):][:nq_job].copy()).to(dev)
+                pr = P.project(ctx, models[m], q, cls.nx, cls.ny, cls.pixel_A)
+                handles.append(pr)
+                jobs.append(dict(proj=pr, imgs=im, ctf=ctf, max_shift=cls.max_shift))
+                evals += per * pr.n * len(cls.ctf)
+    torch.cuda.synchronize()
+    log(f"{len(jobs)} jobs, {evals} evaluations per call")
+    res, outs = {}, {}
+    for mode in ("persistent", "per_job"):
+        for w in range(max(1, args.warmup)):
+            P.logpost_batch(ctx, jobs, prec=args.prec, mode=mode, device_out=True)
+        torch.cuda.synchronize()
+        ctx.set_timing(True)
+        t0 = time.perf_counter()
+        for k in range(args.steps):
+            outs[mode] = P.logpost_batch(ctx, jobs, prec=args.prec, mode=mode, device_out=True)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / args.steps
+        kms, launches, _ = ctx.kernel_time()
+        ctx.set_timing(False)
+        res[mode] = dict(dt=dt, kms=kms / args.steps, launches=launches // args.steps)
+        log(f"{mode}: {dt * 1e3:.2f} ms per call, main kernels {kms / args.steps:.2f} ms in "
+            f"{launches // args.steps} launches")
+    same = all(bool(torch.equal(a["logp"], b["logp"])) for a, b in zip(outs["persistent"], outs["per_job"]))
+    p, q = res["persistent"], res["per_job"]
+    line = {"metric": METRIC + " (many small jobs)", "value": evals / p["dt"], "unit": "evals/s", "n_gpus": 1,
+            "steps": args.steps, "warmup": args.warmup, "ms_per_step": p["dt"] * 1e3, "higher_is_better": True,
+            "scaling": "weak", "vs_baseline": None, "dtype": args.prec, "data": "synthetic",
+            "config": {"workload": f"{len(jobs)} jobs: 96/128/180/224 px x 2 models x {reps}, {per} images x "
+                                   f"{nq_job} orientations each, the class CTF grids (4-16 sets) and windows",
+                       "evals_per_step": evals, "prec": args.prec, "step": "bioem_logpost_batch"},
+            "persistent": {"ms_per_call": p["dt"] * 1e3, "kernel_ms": p["kms"], "launches": p["launches"]},
+            "per_job": {"value": evals / q["dt"], "ms_per_call": q["dt"] * 1e3, "kernel_ms": q["kms"],
+                        "launches": q["launches"]},
+            "persistent_over_per_job": q["dt"] / p["dt"],
+            "kernel_persistent_over_per_job": q["kms"] / max(p["kms"], 1e-9),
+            "identical_results": same}
+    print(json.dumps(line), flush=True)
+    for h in handles:
+        h.free()
+    ctx.close()
+    return 0
+
+
 def run_proposal(args, P, ctx, torch, dev) -> int:
     """128^2 images over 36,864 orientations x 4 CTF sets: the exhaustive
     posterior against the learned proposal (network top-K orientations per
@@ -539,6 +616,8 @@ def run_proposal(args, P, ctx, torch, dev) -> int:
     held_n = args.images
     wl = make_workload(5, n_images=held_n)
     held = wl.classes[0]
+    if args.snr is not None:
+        held.snr = args.snr
     model = wl.models[0]
     model_dev = torch.from_numpy(model).to(dev)
     nq, nc, S = len(held.quats), len(held.ctf), held.max_shift
@@ -546,11 +625,13 @@ def run_proposal(args, P, ctx, torch, dev) -> int:
     ctf = torch.from_numpy(held.ctf).to(dev)
     log(f"training set: {args.train_images} images labelled over {nq} orientations x {nc} CTF sets")
     tr = proposal_training_images(args.train_images)
+    tr.snr = held.snr
     data = PR.make_training_set(ctx, model, tr, proj, T=32, chunk=2000, log=log)
-    net = P.Net(ctx, held.nx, 32, 64, 64, 64, 32, nq)
+    ch = [int(c) for c in args.channels.split(",")]
+    net = P.Net(ctx, held.nx, ch[0], ch[1], ch[2], ch[3], 32, nq)
     net.set_params(PR.init_params(net, held.quats))
     t0 = time.perf_counter()
-    losses = PR.train(net, data, epochs=args.epochs, batch=256, lr=1e-3, log=log)
+    losses = PR.train(net, data, epochs=args.epochs, batch=256, lr=1e-3, log=log, plateau=args.plateau)
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t0
     label_s, label_mass = data.seconds, float(np.median(data.mass))
@@ -607,14 +688,18 @@ def run_proposal(args, P, ctx, torch, dev) -> int:
                      + ", f64 likelihood",
             "data": "synthetic",
             "config": {"workload": f"128x128 px at 2.31 A/px, 1000-sphere model, {held_n} held-out images x "
-                                   f"{nq} orientations x {nc} CTF sets, shifts +-{S}; top-{args.topk} "
-                                   f"proposal, exhaustive fallback below mass {args.tau}",
+                                   f"{nq} orientations x {nc} CTF sets, shifts +-{S}, SNR {held.snr}; "
+                                   f"top-{args.topk} proposal, exhaustive fallback below mass {args.tau}",
+                       "network": {"channels": ch, "hidden": 32},
                        "evals_per_step": evals, "prec": args.prec},
             "exhaustive": {"value": evals / tex, "ms_per_step": tex * 1e3},
             "speedup_vs_exhaustive": tex / tpr,
             "dlogp": {"max": float(d.max()), "median": float(np.median(d)),
                       "frac_le_0.1": float(np.mean(d <= 0.1)), "min": float(d.min())},
             "fallback_fraction": float(r.fallback.mean()),
+            "accepted": {"fraction": float(1.0 - r.fallback.mean()),
+                         "dlogp_max": float(d[~r.fallback].max()) if (~r.fallback).any() else None,
+                         "frac_le_0.1": float(np.mean(d[~r.fallback] <= 0.1)) if (~r.fallback).any() else None},
             "pruned_only": {"dlogp_median": float(np.median(d0)), "frac_le_0.1": float(np.mean(d0 <= 0.1)),
                             "random_topk_fraction_of_grid": args.topk / nq,
                             "network_mass_median": float(np.median(r0.mass)),
@@ -622,7 +707,7 @@ def run_proposal(args, P, ctx, torch, dev) -> int:
             "evals_computed_fraction": r.evals / evals,
             "plain_f32": {"value": plain_rate, "images": npl, "speedup_of_proposal_form": (evals / tpr) / plain_rate,
                           "dlogp_max_vs_proposal_form": float(d_pl.max())},
-            "training": {"images": args.train_images, "epochs": args.epochs, "seconds": t_train,
+            "training": {"images": args.train_images, "epochs": len(losses), "seconds": t_train,
                          "label_seconds": label_s, "loss_per_epoch": losses,
                          "label_mass_top32_median": label_mass}}
     print(json.dumps(line), flush=True)

@@ -533,12 +533,7 @@ __global__ __launch_bounds__(64 * kMfWaves, kMfBlocksPerCU) void k_logpost_mf32(
             }
           }
         }
-#pragma unroll
-        for (int tt = 0; tt < 2; ++tt)
-#pragma unroll
-          for (int b = 0; b < 4; ++b) d1[tt][b] = f4{0.f, 0.f, 0.f, 0.f};
-        cre = 0.f;
-        cim = 0.f;
+        // d1, cre and cim are restarted by the next half group's first K-step
       };
 
       // one consumed K-step st (K-step s1 of its half group); tc / tsc hold
@@ -585,14 +580,17 @@ __global__ __launch_bounds__(64 * kMfWaves, kMfBlocksPerCU) void k_logpost_mf32(
           tc = Tb[(size_t)sn * 64 + lane];
           if constexpr (kPK) tsc = Tb[tmain + (size_t)min(st + 2, KS1 - 1) * 4 + g];
         }
-        d1[0][0] = mma(o.u0r, bf.x, d1[0][0]);
-        d1[1][0] = mma(o.u0i, bf.x, d1[1][0]);
-        d1[0][1] = mma(o.v0r, bf.y, d1[0][1]);
-        d1[1][1] = mma(o.v0i, bf.y, d1[1][1]);
-        d1[0][2] = mma(o.u1r, bf.z, d1[0][2]);
-        d1[1][2] = mma(o.u1i, bf.z, d1[1][2]);
-        d1[0][3] = mma(o.v1r, bf.w, d1[0][3]);
-        d1[1][3] = mma(o.v1i, bf.w, d1[1][3]);
+        // the first K-step of a half group starts its accumulators (a zero
+        // C operand instead of clearing 32 registers)
+        const f4 z4 = f4{0.f, 0.f, 0.f, 0.f};
+        d1[0][0] = mma(o.u0r, bf.x, kSP ? z4 : d1[0][0]);
+        d1[1][0] = mma(o.u0i, bf.x, kSP ? z4 : d1[1][0]);
+        d1[0][1] = mma(o.v0r, bf.y, kSP ? z4 : d1[0][1]);
+        d1[1][1] = mma(o.v0i, bf.y, kSP ? z4 : d1[1][1]);
+        d1[0][2] = mma(o.u1r, bf.z, kSP ? z4 : d1[0][2]);
+        d1[1][2] = mma(o.u1i, bf.z, kSP ? z4 : d1[1][2]);
+        d1[0][3] = mma(o.v1r, bf.w, kSP ? z4 : d1[0][3]);
+        d1[1][3] = mma(o.v1i, bf.w, kSP ? z4 : d1[1][3]);
       };
 
       // CTF values of steps 0 and 1 (KS1 >= 2), in the two register sets

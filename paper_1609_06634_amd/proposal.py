@@ -154,8 +154,11 @@ def make_training_set(ctx: B.Context, model: np.ndarray, cls, proj_grid: B.Proje
 
 
 def train(net: B.Net, data: TrainingSet, epochs: int = 4, batch: int = 256, lr: float = 1e-3,
-          seed: int = 0, log=None) -> list:
-    """Adam on shuffled mini-batches; returns the mean loss of every epoch."""
+          seed: int = 0, log=None, plateau: float = 0.0, patience: int = 3) -> list:
+    """Adam on shuffled mini-batches; returns the mean loss of every epoch.
+    With plateau > 0 training stops early once the best epoch loss has not
+    improved by that relative amount for ``patience`` epochs (at most
+    ``epochs`` in all)."""
     import torch
     rng = np.random.default_rng(seed)
     n = data.inputs.shape[0]
@@ -175,6 +178,12 @@ def train(net: B.Net, data: TrainingSet, epochs: int = 4, batch: int = 256, lr: 
         losses.append(tot / max(cnt, 1))
         if log:
             log(f"epoch {ep + 1}/{epochs}: loss {losses[-1]:.4f}")
+        if plateau > 0.0 and len(losses) > patience:
+            before = min(losses[:-patience])
+            if min(losses[-patience:]) > before * (1.0 - plateau):
+                if log:
+                    log(f"loss plateau after {ep + 1} epochs")
+                break
     return losses
 
 

@@ -79,3 +79,45 @@ def test_trained_network_gains_over_untrained(setup):
     _say(f"fallback {exact.mean():.2f}, evaluations computed {frac:.3f} of exhaustive")
     assert frac < 1.0
     net.close()
+
+
+def test_config5_grid_and_snr_capture_report():
+    """At the proposal workload's own size and signal (36,864 orientations,
+    SNR 0.1, top 256), with a short training run (5,000 labelled images, 3
+    epochs): reports the fraction of held-out images the pruned posterior
+    captures (|d log P| <= 0.1 against the exhaustive judge) and the
+    evaluations the mass fallback saves, and checks what must hold whatever
+    the network learned: the pruned value never exceeds the exhaustive one,
+    and fallen-back images are exact."""
+    import torch
+    import paper_1609_06634_amd as P
+    from paper_1609_06634_amd import proposal as PR
+    P.load()
+    ctx = P.Context(0)
+    dev = torch.device("cuda", 0)
+    wl = make_workload(5, n_images=100)
+    held = wl.classes[0]
+    model = wl.models[0]
+    nq = len(held.quats)
+    proj = P.project(ctx, torch.from_numpy(model).to(dev), torch.from_numpy(held.quats).to(dev), held.nx, held.ny,
+                     held.pixel_A)
+    tr = proposal_training_images(5000)
+    _say(f"config-5 size: labelling 5000 images over {nq} orientations at SNR {held.snr}")
+    data = PR.make_training_set(ctx, model, tr, proj, T=32)
+    net = P.Net(ctx, 128, 32, 64, 128, 128, 32, nq)
+    net.set_params(PR.init_params(net, held.quats))
+    PR.train(net, data, epochs=3, batch=256, lr=1e-3)
+    imgs = PR.render_class_images(ctx, torch.from_numpy(model).to(dev), held, 0, 100)
+    ctf = torch.from_numpy(held.ctf).to(dev)
+    im = P.prepare_images(ctx, imgs)
+    ex = P.logpost(ctx, proj, im, ctf, held.max_shift, prec="split_f16")["logp"]
+    pr = PR.score_with_proposal(ctx, net, proj, imgs, ctf, held.max_shift, K=256, tau=0.0)
+    fb = PR.score_with_proposal(ctx, net, proj, imgs, ctf, held.max_shift, K=256, tau=0.5)
+    d = ex - pr.logp
+    saved = 1.0 - fb.evals / (100 * nq * len(held.ctf))
+    _say(f"captured (|d| <= 0.1): {np.mean(d <= 0.1):.3f} (random 256-subset {256 / nq:.4f}); fallback "
+         f"{fb.fallback.mean():.2f}; evaluations saved {saved:.3f}")
+    assert np.all(d >= -1e-6)
+    exact = fb.fallback
+    assert np.abs(fb.logp[exact] - ex[exact]).max(initial=0.0) <= 1e-9 * np.abs(ex).max()
+    net.close()
