@@ -44,6 +44,7 @@
 // the FP64 likelihood terms are added at finalisation.
 #include <algorithm>
 #include <type_traits>
+#include <utility>
 
 #include "common.hpp"
 
@@ -258,6 +259,16 @@ struct MfArgs {
   int ti, ts, n_ti, n_ts;       // pair tile: images x orientation slots
 };
 
+template <typename F, int... I>
+__device__ __forceinline__ void static_for_impl(F&& f, std::integer_sequence<int, I...>) {
+  (f(std::integral_constant<int, I>{}), ...);
+}
+// f(std::integral_constant<int, i>) for i = 0 .. N - 1, unrolled
+template <int N, typename F>
+__device__ __forceinline__ void static_for(F&& f) {
+  static_for_impl(f, std::make_integer_sequence<int, N>{});
+}
+
 constexpr int kMfWaves = 4;     // one wave per SIMD in a workgroup
 constexpr int kMfBlocksPerCU = 3; // three workgroups per CU: three waves per SIMD (at most 168 VGPRs)
 constexpr int kSlotF4 = 136;    // one produced K-step in LDS: [2][64 lanes] float4 + [2][4] (packed column)
@@ -351,6 +362,13 @@ __device__ __forceinline__ Ops ops_special(float4 x0, float4 x1, float4 t, float
 // 3N/4) in its lanes g = 0, and the first half group carries the packed
 // slot's second column (x = nx/2) in lanes p = 0.  The CTF values of a step
 // are loaded two steps ahead into one of two register sets.
+//
+// kSpec: the 224 x 224 box with four or more CTF sets (KS1 = 14, seven half
+// groups, rounds of four K-steps, one pair per group), with every step
+// unrolled so that round boundaries, shared-slot steps and stage 2 fall at
+// compile-time positions and the global loads of a boundary are unconditional
+// (indices clamped): the wait counts before each step are then exact.
+template <bool kSpec>
 __global__ __launch_bounds__(64 * kMfWaves, kMfBlocksPerCU) void k_logpost_mf32(MfArgs ma) {
   extern __shared__ float4 lds_mf[];
   const int n1 = ma.KS1 * 64, n2 = ma.nHG * 128;
@@ -363,9 +381,9 @@ __global__ __launch_bounds__(64 * kMfWaves, kMfBlocksPerCU) void k_logpost_mf32(
 
   const int lane = threadIdx.x & 63, p = lane & 15, g = lane >> 4;
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int KS1 = ma.KS1, nHG = ma.nHG, nsteps = KS1 * nHG;
-  const int G = ma.G, wpp = ma.wpp, R = ma.R, passes = ma.passes;
-  const int lgR = __builtin_ctz(R);   // R is a power of two
+  const int KS1 = kSpec ? 14 : ma.KS1, nHG = kSpec ? 7 : ma.nHG, nsteps = KS1 * nHG;
+  const int G = kSpec ? 1 : ma.G, wpp = kSpec ? kMfWaves : ma.wpp, R = kSpec ? 4 : ma.R, passes = ma.passes;
+  const int lgR = kSpec ? 2 : __builtin_ctz(R);   // R is a power of two
   const int nrounds = (nsteps + R - 1) >> lgR;
   const int nslots = ma.cand ? ma.k : ma.nq;
   const int S = ma.S;
@@ -419,6 +437,15 @@ __global__ __launch_bounds__(64 * kMfWaves, kMfBlocksPerCU) void k_logpost_mf32(
       // one float4 per lane of the first 16), then its folded products
       float4 pf0, pf1, pf2, pf3, pfs;
       auto load = [&](int rr) {
+        if constexpr (kSpec) {   // unconditional: indices past the last step are clamped
+          const int st = min((rr << lgR) + kp, nsteps - 1);
+          const size_t o = ((size_t)st * 64 + lane) * 2;
+          pf0 = Ib[o]; pf1 = Ib[o + 1]; pf2 = Pb[o]; pf3 = Pb[o + 1];
+          const int gs = (lane >> 2) & 3, which = lane & 3;
+          const size_t os = main_len + ((size_t)min(st, KS1 - 1) * 4 + gs) * 2 + (which & 1);
+          pfs = (which < 2 ? Ib : Pb)[os];
+          return;
+        }
         const int st = (rr << lgR) + kp;
         if (st < nsteps) {
           const size_t o = ((size_t)st * 64 + lane) * 2;
@@ -432,7 +459,7 @@ __global__ __launch_bounds__(64 * kMfWaves, kMfBlocksPerCU) void k_logpost_mf32(
       };
       auto produce = [&](int rr) {
         const int st = (rr << lgR) + kp;
-        if (st >= nsteps) return;   // uniform per wave
+        if (!kSpec && st >= nsteps) return;   // uniform per wave (kSpec: folds into the free buffer)
         const int s1 = st % KS1;
         float4* sl = slots + ((rr & 1) * kMfWaves + w) * kSlotF4;
         float4 o0, o1;
@@ -458,6 +485,12 @@ __global__ __launch_bounds__(64 * kMfWaves, kMfBlocksPerCU) void k_logpost_mf32(
       };
       // start of round rr >= 1: every wave has consumed round rr - 1 and made
       // round rr; make round rr + 1 in the freed buffer, load round rr + 2
+      auto boundary_at = [&](int st) {   // kSpec: the caller knows st is a round start
+        const int rr = st >> lgR;
+        __syncthreads();
+        produce(rr + 1);
+        load(rr + 2);
+      };
       auto boundary = [&](int st) {
         if ((st & (R - 1)) == 0 && st > 0) {   // uniform
           const int rr = st >> lgR;
@@ -482,8 +515,9 @@ __global__ __launch_bounds__(64 * kMfWaves, kMfBlocksPerCU) void k_logpost_mf32(
       // stage 2 of half group h (its stage-1 accumulators are complete);
       // FIRST: h = 0, whose pair 0 is the packed slot and the column nx/4
       auto stage2 = [&](auto FIRST, int h) {
-        // even rows: + (-1)^p (W(N/4) + W(3N/4)) T(N/4) of each column
-        const float sg = (p & 1) ? -1.0f : 1.0f;
+        // even rows: + (-1)^p (W(N/4) + W(3N/4)) T(N/4) of each column (rows
+        // outside the window stay exact zeros)
+        const float sg = 2 * p > S ? 0.0f : ((p & 1) ? -1.0f : 1.0f);
 #pragma unroll
         for (int rr = 0; rr < 4; ++rr) {
           const float xr = __shfl(cre, 4 * g + rr, 64), xi = __shfl(cim, 4 * g + rr, 64);
@@ -528,8 +562,9 @@ __global__ __launch_bounds__(64 * kMfWaves, kMfBlocksPerCU) void k_logpost_mf32(
             const float xu = __shfl(a0u, p, 64), xv = __shfl(a0v, p, 64);
 #pragma unroll
             for (int rr = 0; rr < 4; ++rr) {
-              d2[s][0][rr] += xu;
-              d2[s][1][rr] += xv;
+              const bool in = 2 * (4 * g + rr) <= S;
+              d2[s][0][rr] += in ? xu : 0.f;
+              d2[s][1][rr] += in ? xv : 0.f;
             }
           }
         }
@@ -610,6 +645,29 @@ __global__ __launch_bounds__(64 * kMfWaves, kMfBlocksPerCU) void k_logpost_mf32(
 
       using T_ = std::integral_constant<bool, true>;
       using F_ = std::integral_constant<bool, false>;
+      if constexpr (kSpec) {
+        // first half group: steps 0 .. 13, boundaries at 4, 8, 12
+        static_for<14>([&](auto I) {
+          constexpr int o = decltype(I)::value;
+          if constexpr (o > 0 && (o & 3) == 0) boundary_at(o);
+          if constexpr (o & 1) step(T_{}, std::integral_constant<bool, o == 0>{}, o, o, tb, tsb);
+          else step(T_{}, std::integral_constant<bool, o == 0>{}, o, o, ta, tsa);
+        });
+        stage2(T_{}, 0);
+        // half groups 1 .. 6 in pairs: steps 14 + 28 hp + o, boundaries where
+        // 14 + o is a multiple of 4
+        for (int hp = 0; hp < 3; ++hp) {
+          const int base = 14 + 28 * hp;
+          static_for<28>([&](auto I) {
+            constexpr int o = decltype(I)::value;
+            constexpr int s1 = o % 14;
+            if constexpr (((14 + o) & 3) == 0) boundary_at(base + o);
+            if constexpr (o & 1) step(F_{}, std::integral_constant<bool, s1 == 0>{}, base + o, s1, tb, tsb);
+            else step(F_{}, std::integral_constant<bool, s1 == 0>{}, base + o, s1, ta, tsa);
+            if constexpr (s1 == 13) stage2(F_{}, 1 + 2 * hp + o / 14);
+          });
+        }
+      } else {
       const bool r1 = R == 1;   // a round boundary can fall on an odd step
       // first half group
       boundary(0);
@@ -638,6 +696,7 @@ __global__ __launch_bounds__(64 * kMfWaves, kMfBlocksPerCU) void k_logpost_mf32(
         }
         stage2(F_{}, h);
       }
+      }
       __syncthreads();   // the last round's slots are read before the next group makes round 0
 
       // epilogue of this wave's evaluation (image ic, orientation qc, CTF c)
@@ -648,21 +707,16 @@ __global__ __launch_bounds__(64 * kMfWaves, kMfBlocksPerCU) void k_logpost_mf32(
         if (mine && lane == 0) *out = bioem_erec{-1.0f, 0.0f, -1, 0};
         continue;
       }
-      // X at (+-k, +-dx) from the eight stage-2 products, squared in place
-      // (-1 marks slots outside the window and the duplicates of k = 0, dx = 0)
+      // X at (+-k, +-dx) from the eight stage-2 products, squared in place.
+      // Rows outside the window hold exact zeros (zero coefficients), and the
+      // duplicates of k = 0 and dx = 0 are set to zero here, so every slot
+      // that is not one of the (2S+1)^2 shifts holds X^2 = 0: their terms are
+      // taken off the sum at the end as a count.
       float x2max = 0.0f;
-      // the window masks are recomputed here, not kept live across the loops
-      // (hoisted, they would hold 64 scalar registers)
-      int pe = p, ge = g;
-      asm volatile("" : "+v"(pe), "+v"(ge));
 #pragma unroll
       for (int s = 0; s < 2; ++s) {
-        const int kk = 2 * pe + s;
-        const bool kpos = kk <= S, kneg = kpos && kk > 0;
 #pragma unroll
         for (int rr = 0; rr < 4; ++rr) {
-          const int rho = 4 * ge + rr;
-          const bool ap = 2 * rho <= S, am = ap && rho > 0, bp = 2 * rho + 1 <= S;
           const float Eap = d2[s][0][rr] - d2[s][1][rr], Eam = d2[s][0][rr] + d2[s][1][rr];
           const float Oap = d2[s][2][rr] + d2[s][3][rr], Oam = d2[s][2][rr] - d2[s][3][rr];
           const float Ebp = d2[s][4][rr] - d2[s][5][rr], Ebm = d2[s][4][rr] + d2[s][5][rr];
@@ -670,11 +724,18 @@ __global__ __launch_bounds__(64 * kMfWaves, kMfBlocksPerCU) void k_logpost_mf32(
           float x[8];
           x[0] = Eap - Oap; x[1] = Eap + Oap; x[2] = Eam - Oam; x[3] = Eam + Oam;
           x[4] = Ebp - Obp; x[5] = Ebp + Obp; x[6] = Ebm - Obm; x[7] = Ebm + Obm;
-          const bool ok[8] = {kpos && ap, kpos && am, kneg && ap, kneg && am,
-                              kpos && bp, kpos && bp, kneg && bp, kneg && bp};
+          if (s == 0) {   // k = 0: -k repeats +k
+            const bool k0 = p == 0;
+            x[2] = k0 ? 0.f : x[2]; x[3] = k0 ? 0.f : x[3];
+            x[6] = k0 ? 0.f : x[6]; x[7] = k0 ? 0.f : x[7];
+          }
+          if (rr == 0) {   // dx = 0: -dx repeats +dx
+            const bool r0 = g == 0;
+            x[1] = r0 ? 0.f : x[1]; x[3] = r0 ? 0.f : x[3];
+          }
 #pragma unroll
           for (int v = 0; v < 8; ++v) {
-            const float x2 = ok[v] ? x[v] * x[v] : -1.0f;
+            const float x2 = x[v] * x[v];
             d2[s][v][rr] = x2;
             x2max = fmaxf(x2max, x2);
           }
@@ -685,47 +746,39 @@ __global__ __launch_bounds__(64 * kMfWaves, kMfBlocksPerCU) void k_logpost_mf32(
       const double kappa = ldexp(ma.kscale / (A * Bq), esc);
       const double rho2 = fmin((double)wmax * kappa, 1.0 - 0x1p-52);
       const float cu = (float)(kappa / (1.0 - rho2));
-      const float base = wmax * cu;
       const double n = (double)ma.nx * ma.ny;
       const float c2 = (float)(0.5 * n - 1.0);
-      float sum = 0.0f;
+      const float nzero = (float)(64 * 64 - (2 * S + 1) * (2 * S + 1));
+      // u = (max X^2 - X^2) c_u: >= 0, and exactly 0 at the maximum
+      float sum = 0.0f, f0;
       if (c2 >= 1024.0f) {
-        // log1p(u) by its degree-3 series on [0, 0.05]; a term with u >= 0.05
-        // is below e^-51 of the maximum term (1) and is left out: only values
-        // with X^2 > wmax - 0.05/cu take part (marked slots hold -1, below the
-        // threshold kept at or above -0.5), and a slot left out in every lane
-        // costs no exponential
+        // log1p(u) by its degree-3 series, which is never below log1p(u): a
+        // term with u >= 0.05 is below e^-50 of the maximum term (1) and
+        // stays negligible
         const float c2l2e = c2 * 1.4426950408889634f;
         const float p1 = -c2l2e, p2 = 0.5f * c2l2e, p3 = -c2l2e / 3.0f;
-        const float thr = fmaxf((base - 0.05f) / cu, -0.5f);
+        auto term = [&](float x2) {
+          const float u = (wmax - x2) * cu;
+          return __builtin_amdgcn_exp2f(u * fmaf(u, fmaf(u, p3, p2), p1));
+        };
 #pragma unroll
         for (int s = 0; s < 2; ++s)
 #pragma unroll
           for (int v = 0; v < 8; ++v)
 #pragma unroll
-            for (int rr = 0; rr < 4; ++rr) {
-              const float x2 = d2[s][v][rr];
-              const bool take = x2 > thr;
-              if (__builtin_amdgcn_ballot_w64(take)) {
-                const float u = fminf(fmaxf(fmaf(-x2, cu, base), 0.0f), 0.05f);
-                const float tm = __builtin_amdgcn_exp2f(u * (p1 + u * (p2 + u * p3)));
-                sum += take ? tm : 0.0f;
-              }
-            }
+            for (int rr = 0; rr < 4; ++rr) sum += term(d2[s][v][rr]);
+        f0 = term(0.0f);
       } else {
+        auto term = [&](float x2) { return __expf(-c2 * log1p_f((wmax - x2) * cu)); };
 #pragma unroll
         for (int s = 0; s < 2; ++s)
 #pragma unroll
           for (int v = 0; v < 8; ++v)
 #pragma unroll
-            for (int rr = 0; rr < 4; ++rr) {
-              const float x2 = d2[s][v][rr];
-              const float u = fmaxf(fmaf(-x2, cu, base), 0.0f);
-              const float tm = __expf(-c2 * log1p_f(u));
-              sum += x2 >= 0.0f ? tm : 0.0f;
-            }
+            for (int rr = 0; rr < 4; ++rr) sum += term(d2[s][v][rr]);
+        f0 = term(0.0f);
       }
-      const float tot = wsum_f(sum);
+      const float tot = wsum_f(sum) - nzero * f0;
       if (mine && lane == 0) *out = bioem_erec{wmax, tot, -1, 0};
     }
   }
@@ -821,11 +874,16 @@ hipError_t launch_logpost_mf32(hipStream_t s, const LogpostArgs& a, const float4
   if ((long)ma.n_ti * ma.n_ts > 0x7fffffffL || (long)ma.ti * ma.ts * ma.passes > 0x7fffffffL)
     return hipErrorInvalidValue;
   const size_t smem = mf32_smem_bytes(a.nx, a.ny);
-  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_logpost_mf32),
-                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
+  const bool spec = G.KS1 == 14 && G.nHG == 7 && wpp == kMfWaves;
+  const void* fn = spec ? reinterpret_cast<const void*>(k_logpost_mf32<true>)
+                        : reinterpret_cast<const void*>(k_logpost_mf32<false>);
+  hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
   if (e != hipSuccess) return e;
   const int grid = (int)std::min<long>(groups, (long)kMfBlocksPerCU * mf_device_cus());
-  hipLaunchKernelGGL(k_logpost_mf32, dim3(grid), dim3(64 * kMfWaves), smem, s, ma);
+  if (spec)
+    hipLaunchKernelGGL(k_logpost_mf32<true>, dim3(grid), dim3(64 * kMfWaves), smem, s, ma);
+  else
+    hipLaunchKernelGGL(k_logpost_mf32<false>, dim3(grid), dim3(64 * kMfWaves), smem, s, ma);
   return hipGetLastError();
 }
 
