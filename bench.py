@@ -176,9 +176,9 @@ def main() -> int:
     ap.add_argument("--prec", default="f32", choices=["f32", "split_f16", "split_bf16"])
     ap.add_argument("--images", type=int, default=1000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample", default="16x48x8",
+    ap.add_argument("--cpu-sample", default="16x128x8",
                     help="images x orientations x CTF sets for the oracle's FFT form")
-    ap.add_argument("--cpu-sample-direct", default="2x8x2",
+    ap.add_argument("--cpu-sample-direct", default="2x16x2",
                     help="the same for the oracle's direct correlation")
     ap.add_argument("--workload", default="paper224", choices=["paper224", "mixed", "smalljobs", "proposal",
                                                                    "crossover"],

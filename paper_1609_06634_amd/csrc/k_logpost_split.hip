@@ -390,14 +390,14 @@ __device__ __forceinline__ void split_item(const SplitArgs& sa, const uint4* __r
         const double kappa = ldexp(a.kscale / (A * B), esc);
         const double rho2 = fmin((double)wmax * kappa, 1.0 - 0x1p-52);
         const float cu = (float)(kappa / (1.0 - rho2));
-        const float base = wmax * cu;
-        // Pass 2: sum of (1 + u)^-(n/2-1) over the window.
+        // Pass 2: sum of (1 + u)^-(n/2-1) over the window, u = (max X^2 - X^2) c_u
+        // (exactly 0 at the maximum: no rounding of max X^2 c_u enters every term).
         float sum = 0.0f;
         if (series) {
 #pragma unroll
           for (int k = 0; k < NT * NT * 4; ++k) {
             const float x2 = acc2[e][k / (4 * NT)][(k / 4) % NT][k % 4];
-            const float u = __builtin_amdgcn_fmed3f(fmaf(-x2, cu, base), 0.0f, 0.05f);
+            const float u = fminf((wmax - x2) * cu, 0.05f);
             // slots outside the window are marked x2 = -1 and left out
             const float t = __builtin_amdgcn_exp2f(u * (p1 + u * (p2 + u * p3)));
             sum += x2 >= 0.0f ? t : 0.0f;
@@ -406,7 +406,7 @@ __device__ __forceinline__ void split_item(const SplitArgs& sa, const uint4* __r
 #pragma unroll
           for (int k = 0; k < NT * NT * 4; ++k) {
             const float x2 = acc2[e][k / (4 * NT)][(k / 4) % NT][k % 4];
-            const float u = fmaxf(fmaf(-x2, cu, base), 0.0f);
+            const float u = (wmax - x2) * cu;
             const float t = __expf(-c2 * log1p_acc(u));
             sum += x2 >= 0.0f ? t : 0.0f;
           }
