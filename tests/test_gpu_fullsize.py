@@ -98,3 +98,29 @@ def test_fullsize_sampled_orientations_live(P, setup):
     for j, i in enumerate(sel):
         for q in qs:
             assert abs(out["orient"][i, q] - r.logp_orient[j, q]) <= 0.01, (i, q)
+
+
+@pytest.mark.parametrize("nc", [3, 5])
+def test_224px_partial_ctf_passes(P, nc):
+    """The 224^2 box with CTF set counts that leave waves without a CTF set of
+    their own (3: one idle wave; 5: a second pass with one set), on 12
+    orientations, against the oracle element by element (log P and the
+    per-orientation values)."""
+    wl = make_workload(2, n_images=2)
+    cls = wl.classes[0]
+    imgs = O.render_images(cls, wl.models)
+    rng = np.random.default_rng(224 + nc)
+    quats = np.concatenate([cls.img_quat[:2], cls.quats[rng.choice(len(cls.quats), 10, replace=False)]])
+    ctf = cls.ctf[:nc]
+    _say(f"224^2 partial passes: 2 images x 12 q x {nc} c, S={cls.max_shift}")
+    ctx = P.Context(0)
+    proj = P.project(ctx, wl.models[0], quats, cls.nx, cls.ny, cls.pixel_A)
+    out = P.logpost(ctx, proj, P.prepare_images(ctx, imgs), ctf, cls.max_shift, prec="f32", orient=True)
+    r = O.logpost_oracle(imgs.astype(np.float64), wl.models[0], quats, ctf, cls.pixel_A, cls.max_shift,
+                         method="fft")
+    d = np.abs(out["logp"] - r.logp)
+    _say(f"  max |dlogP| = {d.max():.3e}")
+    assert d.max() <= TOL["f32"], d
+    assert np.abs(out["orient"] - r.logp_orient).max() <= TOL["f32"]
+    assert np.all(out["best"]["status"] == 0)
+    assert np.abs(out["best"]["logl"] - r.best_logl).max() <= TOL["f32"]
