@@ -100,10 +100,11 @@ def test_fullsize_sampled_orientations_live(P, setup):
             assert abs(out["orient"][i, q] - r.logp_orient[j, q]) <= 0.01, (i, q)
 
 
-@pytest.mark.parametrize("nc", [3, 5])
-def test_224px_partial_ctf_passes(P, nc):
-    """The 224^2 box with CTF set counts that leave waves without a CTF set of
-    their own (3: one idle wave; 5: a second pass with one set), on 12
+@pytest.mark.parametrize("nc,S", [(3, 20), (5, 20), (4, 0), (8, 3)])
+def test_224px_partial_ctf_passes(P, nc, S):
+    """The 224^2 box's unrolled step sequence with CTF set counts that leave
+    waves without a CTF set of their own (3: one idle wave; 5: a second pass
+    with one set) and with small shift windows (S = 0, 3), on 12
     orientations, against the oracle element by element (log P and the
     per-orientation values)."""
     wl = make_workload(2, n_images=2)
@@ -112,12 +113,11 @@ def test_224px_partial_ctf_passes(P, nc):
     rng = np.random.default_rng(224 + nc)
     quats = np.concatenate([cls.img_quat[:2], cls.quats[rng.choice(len(cls.quats), 10, replace=False)]])
     ctf = cls.ctf[:nc]
-    _say(f"224^2 partial passes: 2 images x 12 q x {nc} c, S={cls.max_shift}")
+    _say(f"224^2 step sequence: 2 images x 12 q x {nc} c, S={S}")
     ctx = P.Context(0)
     proj = P.project(ctx, wl.models[0], quats, cls.nx, cls.ny, cls.pixel_A)
-    out = P.logpost(ctx, proj, P.prepare_images(ctx, imgs), ctf, cls.max_shift, prec="f32", orient=True)
-    r = O.logpost_oracle(imgs.astype(np.float64), wl.models[0], quats, ctf, cls.pixel_A, cls.max_shift,
-                         method="fft")
+    out = P.logpost(ctx, proj, P.prepare_images(ctx, imgs), ctf, S, prec="f32", orient=True)
+    r = O.logpost_oracle(imgs.astype(np.float64), wl.models[0], quats, ctf, cls.pixel_A, S, method="fft")
     d = np.abs(out["logp"] - r.logp)
     _say(f"  max |dlogP| = {d.max():.3e}")
     assert d.max() <= TOL["f32"], d
