@@ -379,7 +379,7 @@ __global__ __launch_bounds__(64 * kMfWaves, kMfBlocksPerCU) void k_logpost_mf32(
   for (int e = threadIdx.x; e < n1 + n2; e += 64 * kMfWaves) lds_mf[e] = e < n1 ? ma.F1[e] : ma.F2[e - n1];
   __syncthreads();
 
-  const int lane = threadIdx.x & 63, p = lane & 15, g = lane >> 4;
+  int lane = threadIdx.x & 63, p = lane & 15, g = lane >> 4;
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int KS1 = kSpec ? 14 : ma.KS1, nHG = kSpec ? 7 : ma.nHG, nsteps = KS1 * nHG;
   const int G = kSpec ? 1 : ma.G, wpp = kSpec ? kMfWaves : ma.wpp, R = kSpec ? 4 : ma.R, passes = ma.passes;
@@ -403,14 +403,23 @@ __global__ __launch_bounds__(64 * kMfWaves, kMfBlocksPerCU) void k_logpost_mf32(
   const int nwx = ((int)gridDim.x - xcd + kx - 1) / kx;
 
   for (int t = xcd; t < n_tiles; t += kx) {
-    const int tI = t / ma.n_ts, tS = t - tI * ma.n_ts;
+    int dnts = ma.n_ts;
+    asm volatile("" : "+s"(dnts));
+    const int tI = t / dnts, tS = t - tI * dnts;
     for (int gg = lw; gg < groups_per_tile; gg += nwx) {
-      const int pass = gg % passes, grp = gg / passes;
+      // the divisors and the lane index pass through an empty asm at every
+      // group, so that the divisors' reciprocals and the lane-derived
+      // addresses are formed per group instead of being hoisted out of the
+      // loops and held (or spilled to scratch) for the whole kernel
+      int dpass = passes, dti = ma.ti;
+      asm volatile("" : "+s"(dpass), "+s"(dti));
+      asm volatile("" : "+v"(lane), "+v"(p), "+v"(g));
+      const int pass = gg % dpass, grp = gg / dpass;
       // pair (image, slot) of group member m, valid or not
       auto pair_of = [&](int m, int& i, int& slot) -> bool {
         const int pl = grp * G + m;
-        i = tI * ma.ti + pl % ma.ti;
-        slot = tS * ma.ts + pl / ma.ti;
+        i = tI * dti + pl % dti;
+        slot = tS * ma.ts + pl / dti;
         return pl < tile_pairs && i < ma.ni && slot < nslots;
       };
       // the group's first valid pair stands in for its invalid members (a
@@ -746,9 +755,14 @@ __global__ __launch_bounds__(64 * kMfWaves, kMfBlocksPerCU) void k_logpost_mf32(
       const double kappa = ldexp(ma.kscale / (A * Bq), esc);
       const double rho2 = fmin((double)wmax * kappa, 1.0 - 0x1p-52);
       const float cu = (float)(kappa / (1.0 - rho2));
-      const double n = (double)ma.nx * ma.ny;
+      // the box size passes through an empty asm here, so the constants below
+      // are formed in the epilogue instead of being hoisted out of the group
+      // loop and held (or spilled) across all K-steps
+      int npix = ma.nx * ma.ny, Se = S;
+      asm volatile("" : "+s"(npix), "+s"(Se));
+      const double n = (double)npix;
       const float c2 = (float)(0.5 * n - 1.0);
-      const float nzero = (float)(64 * 64 - (2 * S + 1) * (2 * S + 1));
+      const float nzero = (float)(64 * 64 - (2 * Se + 1) * (2 * Se + 1));
       // u = (max X^2 - X^2) c_u: >= 0, and exactly 0 at the maximum
       float sum = 0.0f, f0;
       if (c2 >= 1024.0f) {
