@@ -496,6 +496,11 @@ __global__ __launch_bounds__(64 * kMfWaves, kMfBlocksPerCU) void k_logpost_mf32(
       // round rr; make round rr + 1 in the freed buffer, load round rr + 2
       auto boundary_at = [&](int st) {   // kSpec: the caller knows st is a round start
         const int rr = st >> lgR;
+        // the lane index passes through an empty asm at every round, so that
+        // the lane-derived LDS and global addresses are formed again for each
+        // round rather than held across all of them (held, they exceed the
+        // 168 registers of three waves per SIMD and spill to scratch)
+        asm volatile("" : "+v"(lane), "+v"(p), "+v"(g));
         __syncthreads();
         produce(rr + 1);
         load(rr + 2);
@@ -585,6 +590,7 @@ __global__ __launch_bounds__(64 * kMfWaves, kMfBlocksPerCU) void k_logpost_mf32(
       // group (packed slot); SP: s1 = 0 (shared slot in lanes g = 0).
       auto step = [&](auto PK, auto SP, int st, int s1, float4& tc, float4& tsc) {
         constexpr bool kPK = decltype(PK)::value, kSP = decltype(SP)::value;
+        if constexpr (!kSpec) asm volatile("" : "+v"(lane), "+v"(p), "+v"(g));   // see boundary_at
         const int rr = st >> lgR;
         const float4* sl = slots + ((rr & 1) * kMfWaves + gi * R + (st & (R - 1))) * kSlotF4;
         const float4 x0 = sl[lane], x1 = sl[64 + lane], bf = F1s[s1 * 64 + lane];
@@ -666,6 +672,7 @@ __global__ __launch_bounds__(64 * kMfWaves, kMfBlocksPerCU) void k_logpost_mf32(
         // half groups 1 .. 6 in pairs: steps 14 + 28 hp + o, boundaries where
         // 14 + o is a multiple of 4
         for (int hp = 0; hp < 3; ++hp) {
+          asm volatile("" : "+v"(lane), "+v"(p), "+v"(g));   // see boundary_at
           const int base = 14 + 28 * hp;
           static_for<28>([&](auto I) {
             constexpr int o = decltype(I)::value;
