@@ -124,3 +124,34 @@ def test_224px_partial_ctf_passes(P, nc, S):
     assert np.abs(out["orient"] - r.logp_orient).max() <= TOL["f32"]
     assert np.all(out["best"]["status"] == 0)
     assert np.abs(out["best"]["logl"] - r.best_logl).max() <= TOL["f32"]
+
+
+def test_224px_candidate_lists(P):
+    """The 224^2 step sequence on per-image candidate lists (a proposal's
+    pruned grid): log P over the candidates with the full grid's prior, the
+    reported grid point among them, and the per-orientation values, against
+    the oracle restricted to the same candidates."""
+    wl = make_workload(2, n_images=3)
+    cls = wl.classes[0]
+    imgs = O.render_images(cls, wl.models)
+    rng = np.random.default_rng(2245)
+    nq = 12
+    quats = np.concatenate([cls.img_quat[:3], cls.quats[rng.choice(len(cls.quats), nq - 3, replace=False)]])
+    cand = np.stack([np.sort(rng.choice(nq, 5, replace=False)) for _ in range(3)]).astype(np.int32)
+    ctf = cls.ctf[:4]
+    _say(f"224^2 candidate lists: 3 images x 5 of {nq} q x 4 c, S={cls.max_shift}")
+    ctx = P.Context(0)
+    proj = P.project(ctx, wl.models[0], quats, cls.nx, cls.ny, cls.pixel_A)
+    out = P.logpost(ctx, proj, P.prepare_images(ctx, imgs), ctf, cls.max_shift, prec="f32", cand_q=cand,
+                    orient=True)
+    for i in range(3):
+        r = O.logpost_oracle(imgs[i:i + 1].astype(np.float64), wl.models[0], quats, ctf, cls.pixel_A,
+                             cls.max_shift, method="fft", q_subset=list(cand[i]))
+        d = abs(out["logp"][i] - r.logp[0])
+        _say(f"  image {i}: |dlogP| = {d:.3e}")
+        assert d <= TOL["f32"]
+        assert out["best"]["q"][i] in set(cand[i].tolist())
+        mask = np.zeros(nq, bool)
+        mask[cand[i]] = True
+        assert np.all(np.isneginf(out["orient"][i][~mask]))
+        assert np.abs(out["orient"][i][mask] - r.logp_orient[0][mask]).max() <= TOL["f32"]
