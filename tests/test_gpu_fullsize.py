@@ -100,13 +100,13 @@ def test_fullsize_sampled_orientations_live(P, setup):
             assert abs(out["orient"][i, q] - r.logp_orient[j, q]) <= 0.01, (i, q)
 
 
-@pytest.mark.parametrize("nc,S", [(3, 20), (5, 20), (4, 0), (8, 3)])
+@pytest.mark.parametrize("nc,S", [(3, 20), (5, 20), (4, 0), (8, 3), (4, 31)])
 def test_224px_partial_ctf_passes(P, nc, S):
     """The 224^2 box's unrolled step sequence with CTF set counts that leave
     waves without a CTF set of their own (3: one idle wave; 5: a second pass
-    with one set) and with small shift windows (S = 0, 3), on 12
-    orientations, against the oracle element by element (log P and the
-    per-orientation values)."""
+    with one set), with small shift windows (S = 0, 3) and with the largest
+    window the matrix-core path takes (S = 31), on 12 orientations, against
+    the oracle element by element (log P and the per-orientation values)."""
     wl = make_workload(2, n_images=2)
     cls = wl.classes[0]
     imgs = O.render_images(cls, wl.models)
