@@ -273,6 +273,11 @@ constexpr int kMfWaves = 4;     // one wave per SIMD in a workgroup
 constexpr int kMfBlocksPerCU = 3; // three workgroups per CU: three waves per SIMD (at most 168 VGPRs)
 constexpr int kSlotF4 = 136;    // one produced K-step in LDS: [2][64 lanes] float4 + [2][4] (packed column)
 
+// 16-byte load through a buffer resource: voffset per lane, soffset uniform
+__device__ __forceinline__ float4 bld4(__amdgpu_buffer_rsrc_t r, int vo, int so) {
+  return __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(r, vo, so, 0));
+}
+
 __device__ __forceinline__ f4 mma(float a, float b, f4 c) {
   return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
 }
@@ -441,18 +446,34 @@ __global__ __launch_bounds__(64 * kMfWaves, kMfBlocksPerCU) void k_logpost_mf32(
       const float4* Ib = ma.im + (size_t)ip * ma.len;
       const float4* Pb = ma.pm + (size_t)qp * ma.len;
       const float4* Tb = ma.tm + (size_t)cc * ma.tlen;
+      // buffer resources of the three items (the box's loads take their
+      // offsets as a lane part and a uniform part, with no 64-bit address
+      // arithmetic per load)
+      constexpr int kRsrcW3 = 0x00020000;
+      auto rsrc = [](const float4* q, size_t n) {   // q is uniform: taken from lane 0
+        const uint64_t a = (uint64_t)q;
+        const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)a);
+        const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(a >> 32));
+        void* u = (void*)(((uint64_t)hi << 32) | lo);
+        return __builtin_amdgcn_make_buffer_rsrc(u, 0, (int)(n * 16), kRsrcW3);
+      };
+      const __amdgpu_buffer_rsrc_t rI = rsrc(Ib, ma.len), rP = rsrc(Pb, ma.len), rT = rsrc(Tb, ma.tlen);
 
       // producer: loads of one K-step (and the packed slot's second column,
       // one float4 per lane of the first 16), then its folded products
       float4 pf0, pf1, pf2, pf3, pfs;
-      auto load = [&](int rr) {
+      auto load = [&](int rr, auto PFS) {
         if constexpr (kSpec) {   // unconditional: indices past the last step are clamped
           const int st = min((rr << lgR) + kp, nsteps - 1);
-          const size_t o = ((size_t)st * 64 + lane) * 2;
-          pf0 = Ib[o]; pf1 = Ib[o + 1]; pf2 = Pb[o]; pf3 = Pb[o + 1];
-          const int gs = (lane >> 2) & 3, which = lane & 3;
-          const size_t os = main_len + ((size_t)min(st, KS1 - 1) * 4 + gs) * 2 + (which & 1);
-          pfs = (which < 2 ? Ib : Pb)[os];
+          const int vo = lane * 32, so = st * 2048;
+          pf0 = bld4(rI, vo, so); pf1 = bld4(rI, vo + 16, so);
+          pf2 = bld4(rP, vo, so); pf3 = bld4(rP, vo + 16, so);
+          if constexpr (decltype(PFS)::value) {   // a round that can hold first-half-group steps
+            const int gs = (lane >> 2) & 3, which = lane & 3;
+            const int vs = gs * 32 + (which & 1) * 16, ss = (int)(main_len * 16) + min(st, KS1 - 1) * 128;
+            if (which < 2) pfs = bld4(rI, vs, ss);
+            else pfs = bld4(rP, vs, ss);
+          }
           return;
         }
         const int st = (rr << lgR) + kp;
@@ -494,7 +515,7 @@ __global__ __launch_bounds__(64 * kMfWaves, kMfBlocksPerCU) void k_logpost_mf32(
       };
       // start of round rr >= 1: every wave has consumed round rr - 1 and made
       // round rr; make round rr + 1 in the freed buffer, load round rr + 2
-      auto boundary_at = [&](int st) {   // kSpec: the caller knows st is a round start
+      auto boundary_at = [&](int st, auto PFS) {   // kSpec: the caller knows st is a round start
         const int rr = st >> lgR;
         // the lane index passes through an empty asm at every round, so that
         // the lane-derived LDS and global addresses are formed again for each
@@ -503,14 +524,14 @@ __global__ __launch_bounds__(64 * kMfWaves, kMfBlocksPerCU) void k_logpost_mf32(
         asm volatile("" : "+v"(lane), "+v"(p), "+v"(g));
         __syncthreads();
         produce(rr + 1);
-        load(rr + 2);
+        load(rr + 2, PFS);
       };
       auto boundary = [&](int st) {
         if ((st & (R - 1)) == 0 && st > 0) {   // uniform
           const int rr = st >> lgR;
           __syncthreads();
           if (rr + 1 < nrounds) produce(rr + 1);
-          if (rr + 2 < nrounds) load(rr + 2);
+          if (rr + 2 < nrounds) load(rr + 2, std::true_type{});
         }
       };
 
@@ -625,7 +646,11 @@ __global__ __launch_bounds__(64 * kMfWaves, kMfBlocksPerCU) void k_logpost_mf32(
         // this register set now takes the CTF values of step st + 2 (the
         // load is unconditional, clamped to the last step, so that no copy
         // of the old values has to wait for it)
-        {
+        if constexpr (kSpec) {
+          const int sn = min(st + 2, nsteps - 1);
+          tc = bld4(rT, lane * 16, sn * 1024);
+          if constexpr (kPK) tsc = bld4(rT, g * 16, (int)(tmain * 16) + min(st + 2, KS1 - 1) * 64);
+        } else {
           const int sn = min(st + 2, nsteps - 1);
           tc = Tb[(size_t)sn * 64 + lane];
           if constexpr (kPK) tsc = Tb[tmain + (size_t)min(st + 2, KS1 - 1) * 4 + g];
@@ -651,12 +676,12 @@ __global__ __launch_bounds__(64 * kMfWaves, kMfBlocksPerCU) void k_logpost_mf32(
         tsb = Tb[tmain + 4 + g];
       }
 
-      load(0);
+      load(0, std::true_type{});
       produce(0);
-      if (nrounds > 1) load(1);
+      if (nrounds > 1) load(1, std::true_type{});
       __syncthreads();
       if (nrounds > 1) produce(1);
-      if (nrounds > 2) load(2);
+      if (nrounds > 2) load(2, std::true_type{});
 
       using T_ = std::integral_constant<bool, true>;
       using F_ = std::integral_constant<bool, false>;
@@ -664,7 +689,9 @@ __global__ __launch_bounds__(64 * kMfWaves, kMfBlocksPerCU) void k_logpost_mf32(
         // first half group: steps 0 .. 13, boundaries at 4, 8, 12
         static_for<14>([&](auto I) {
           constexpr int o = decltype(I)::value;
-          if constexpr (o > 0 && (o & 3) == 0) boundary_at(o);
+          // the round loaded at o holds steps 4 (o / 4 + 2) .. + 3: first
+          // half group steps (below 14) only for o = 4
+          if constexpr (o > 0 && (o & 3) == 0) boundary_at(o, std::integral_constant<bool, o == 4>{});
           if constexpr (o & 1) step(T_{}, std::integral_constant<bool, o == 0>{}, o, o, tb, tsb);
           else step(T_{}, std::integral_constant<bool, o == 0>{}, o, o, ta, tsa);
         });
@@ -677,7 +704,7 @@ __global__ __launch_bounds__(64 * kMfWaves, kMfBlocksPerCU) void k_logpost_mf32(
           static_for<28>([&](auto I) {
             constexpr int o = decltype(I)::value;
             constexpr int s1 = o % 14;
-            if constexpr (((14 + o) & 3) == 0) boundary_at(base + o);
+            if constexpr (((14 + o) & 3) == 0) boundary_at(base + o, std::false_type{});
             if constexpr (o & 1) step(F_{}, std::integral_constant<bool, s1 == 0>{}, base + o, s1, tb, tsb);
             else step(F_{}, std::integral_constant<bool, s1 == 0>{}, base + o, s1, ta, tsa);
             if constexpr (s1 == 13) stage2(F_{}, 1 + 2 * hp + o / 14);
