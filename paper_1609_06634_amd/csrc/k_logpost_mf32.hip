@@ -469,10 +469,12 @@ __global__ __launch_bounds__(64 * kMfWaves, kMfBlocksPerCU) void k_logpost_mf32(
           pf0 = bld4(rI, vo, so); pf1 = bld4(rI, vo + 16, so);
           pf2 = bld4(rP, vo, so); pf3 = bld4(rP, vo + 16, so);
           if constexpr (decltype(PFS)::value) {   // a round that can hold first-half-group steps
+            // lanes 0, 1 of each four take the image, lanes 2, 3 the projection: both
+            // are loaded and one is kept, as a resource cannot differ between lanes
             const int gs = (lane >> 2) & 3, which = lane & 3;
             const int vs = gs * 32 + (which & 1) * 16, ss = (int)(main_len * 16) + min(st, KS1 - 1) * 128;
-            if (which < 2) pfs = bld4(rI, vs, ss);
-            else pfs = bld4(rP, vs, ss);
+            const float4 si = bld4(rI, vs, ss), sp = bld4(rP, vs, ss);
+            pfs = which < 2 ? si : sp;
           }
           return;
         }
