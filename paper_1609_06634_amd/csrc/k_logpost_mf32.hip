@@ -446,9 +446,11 @@ __global__ __launch_bounds__(64 * kMfWaves, kMfBlocksPerCU) void k_logpost_mf32(
       const float4* Ib = ma.im + (size_t)ip * ma.len;
       const float4* Pb = ma.pm + (size_t)qp * ma.len;
       const float4* Tb = ma.tm + (size_t)cc * ma.tlen;
-      // buffer resources of the three items (the box's loads take their
-      // offsets as a lane part and a uniform part, with no 64-bit address
-      // arithmetic per load)
+      // buffer resources of the three items: the loads below take their
+      // offsets as a lane part (a register) and a uniform part (formed on the
+      // scalar unit), with no 64-bit address arithmetic per load.  Word 3 of
+      // a gfx9 resource: 32-bit data format, no swizzle or stride; the range
+      // is the item's length (mf32_supported bounds it far below 2^31 bytes).
       constexpr int kRsrcW3 = 0x00020000;
       auto rsrc = [](const float4* q, size_t n) {   // q is uniform: taken from lane 0
         const uint64_t a = (uint64_t)q;
@@ -480,12 +482,14 @@ __global__ __launch_bounds__(64 * kMfWaves, kMfBlocksPerCU) void k_logpost_mf32(
         }
         const int st = (rr << lgR) + kp;
         if (st < nsteps) {
-          const size_t o = ((size_t)st * 64 + lane) * 2;
-          pf0 = Ib[o]; pf1 = Ib[o + 1]; pf2 = Pb[o]; pf3 = Pb[o + 1];
-          if (st < KS1 && lane < 16) {   // first half group: the packed slot
-            const int gs = lane >> 2, which = lane & 3;
-            const size_t os = main_len + ((size_t)st * 4 + gs) * 2 + (which & 1);
-            pfs = which < 2 ? Ib[os] : Pb[os];
+          const int vo = lane * 32, so = st * 2048;
+          pf0 = bld4(rI, vo, so); pf1 = bld4(rI, vo + 16, so);
+          pf2 = bld4(rP, vo, so); pf3 = bld4(rP, vo + 16, so);
+          if (st < KS1) {   // first half group: the packed slot (used by lanes 0 .. 15)
+            const int gs = (lane >> 2) & 3, which = lane & 3;
+            const int vs = gs * 32 + (which & 1) * 16, ss = (int)(main_len * 16) + st * 128;
+            const float4 si = bld4(rI, vs, ss), sp = bld4(rP, vs, ss);
+            pfs = which < 2 ? si : sp;
           }
         }
       };
@@ -648,14 +652,10 @@ __global__ __launch_bounds__(64 * kMfWaves, kMfBlocksPerCU) void k_logpost_mf32(
         // this register set now takes the CTF values of step st + 2 (the
         // load is unconditional, clamped to the last step, so that no copy
         // of the old values has to wait for it)
-        if constexpr (kSpec) {
+        {
           const int sn = min(st + 2, nsteps - 1);
           tc = bld4(rT, lane * 16, sn * 1024);
           if constexpr (kPK) tsc = bld4(rT, g * 16, (int)(tmain * 16) + min(st + 2, KS1 - 1) * 64);
-        } else {
-          const int sn = min(st + 2, nsteps - 1);
-          tc = Tb[(size_t)sn * 64 + lane];
-          if constexpr (kPK) tsc = Tb[tmain + (size_t)min(st + 2, KS1 - 1) * 4 + g];
         }
         // the first K-step of a half group starts its accumulators (a zero
         // C operand instead of clearing 32 registers)
