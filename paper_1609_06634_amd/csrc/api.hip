@@ -90,6 +90,7 @@ struct Job {
   size_t len = 0;                  // stored spectrum stride
   int kernel = 0, ti = 0, ts = 0;  // bioem_opts kernel form and item tile (0 = default)
   bool mf = false;                 // F32 on the FP32 matrix cores
+  int zs = 0;                      // split forms: operand scale exponent (CTF tile copies times 2^zs)
   DevMem mftab, mftm;              // its operand tables and orbit-order CTF tables
   Job() = default;
   Job(Job&&) = default;
@@ -185,7 +186,8 @@ bioem_status plan_job(bioem_ctx* ctx, const bioem_job& jb, int prec, int out_mem
   HIP_OR_FAIL(ctx, launch_ctf_table(s, J.dctf.as<double>(), nc, nx, ny, proj->pixel, J.table.as<float>()));
   if (split) {
     HIP_OR_FAIL(ctx, J.ttable.get(sizeof(float4) * tile_table_len(nx, ny) * nc, carve));
-    HIP_OR_FAIL(ctx, launch_tile_table(s, J.table.as<float>(), nc, nx, ny, J.ttable.as<float4>()));
+    J.zs = split_operand_scale(ny);
+    HIP_OR_FAIL(ctx, launch_tile_table(s, J.table.as<float>(), nc, nx, ny, J.zs, J.ttable.as<float4>()));
   }
   if (mf) {
     HIP_OR_FAIL(ctx, J.mftab.get(sizeof(float4) * mf32_table_len(nx, ny), carve));
@@ -195,6 +197,10 @@ bioem_status plan_job(bioem_ctx* ctx, const bioem_job& jb, int prec, int out_mem
   }
   HIP_OR_FAIL(ctx, launch_proj_norms(s, proj->spec, proj->expo, nq, J.table.as<float>(), nc, nx, ny,
                                      J.B.as<double>()));
+  // the split forms read the table (packed column, best-displacement pass)
+  // with the same operand scale as its tile copies; the norms above are taken
+  // first, and the best-displacement pass only compares values
+  if (split && J.zs) HIP_OR_FAIL(ctx, launch_scale_table(s, J.table.as<float>(), J.len * nc, J.zs));
   J.logp = jb.logp; J.best = jb.best; J.orient = jb.logp_orient;
   J.d_logp = jb.logp; J.d_best = jb.best; J.d_orient = jb.logp_orient;
   if (out_mem == BIOEM_MEM_HOST) {
@@ -218,6 +224,7 @@ LogpostArgs job_args(const Job& J, int i0, int cn, bioem_erec* rec) {
   a.cand = J.has_cand ? J.dcand.as<int32_t>() + (size_t)i0 * J.k : nullptr; a.k = J.k;
   a.rec = rec;
   a.kscale = 1.0 / ((double)J.nx * J.ny * (double)J.nx * J.ny);
+  a.zs = J.zs;
   return a;
 }
 

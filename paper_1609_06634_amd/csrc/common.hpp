@@ -94,7 +94,11 @@ hipError_t launch_euler_quat(hipStream_t s, const double* euler, int n, double* 
 // Fragment-order copies: complex spectra [n][nx/2+1][spec_ld(ny)] -> [n][tile_spec_len],
 // real tables [n][nx/2+1][spec_ld(ny)] -> [n][tile_table_len] (rows l = 32 ks + 8 g + 4 r .. +3, r < 2).
 hipError_t launch_tile_spec(hipStream_t s, const float2* spec, int n, int nx, int ny, float4* tile);
-hipError_t launch_tile_table(hipStream_t s, const float* table, int n, int nx, int ny, float4* tile);
+hipError_t launch_tile_table(hipStream_t s, const float* table, int n, int nx, int ny, int zs, float4* tile);
+// Exponent zs of the split forms' operand scale 2^zs for an ny-row box, and
+// the scaling of n table values by 2^zs (exact).
+int split_operand_scale(int ny);
+hipError_t launch_scale_table(hipStream_t s, float* table, size_t n, int zs);
 hipError_t launch_render(hipStream_t s, const float2* spec, const int32_t* expo, int n, int nx,
                          int ny, double pixel, const double* ctf, const int32_t* shifts,
                          const double* norm_offset, const float* noise, double snr,
@@ -134,6 +138,7 @@ struct LogpostArgs {
   const int32_t* cand; int k;     // [ni][k] chunk-relative rows, or null
   bioem_erec* rec;                // [ni][nq or k][nc]
   double kscale;                  // (2^e_i 2^e_q / n)^2 kappa factor: 1 / n^2
+  int zs;                         // split forms: ttile holds the CTF values times 2^zs
 };
 hipError_t launch_logpost_f32(hipStream_t s, const LogpostArgs& a);
 // Recompute the argmax displacement (FP32 transform) of best[i]'s (q, c).

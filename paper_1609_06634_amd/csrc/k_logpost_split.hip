@@ -160,7 +160,8 @@ __device__ __forceinline__ void split_item(const SplitArgs& sa, const uint4* __r
     const float4* Ot = a.itile + (size_t)i * tlen;
     const float4* Pt = a.ptile + (size_t)q * tlen;
     const double A = a.istats[3 * i + 2];
-    const int esc = 2 * (a.iexpo[i] + a.pexpo[q]);
+    // X carries the operand scale 2^zs of the CTF values: kappa takes it off
+    const int esc = 2 * (a.iexpo[i] + a.pexpo[q]) - 2 * a.zs;
     const int c0 = cg * EW;
     bioem_erec* out = a.rec + ((size_t)i * nslots + slot) * a.nc;
 
@@ -412,7 +413,7 @@ __device__ __forceinline__ void split_item(const SplitArgs& sa, const uint4* __r
           }
         }
         const float tot = wave_sum_f(sum);
-        if (lane == 0) out[c] = bioem_erec{wmax, tot, -1, 0};
+        if (lane == 0) out[c] = bioem_erec{ldexpf(wmax, -2 * a.zs), tot, -1, 0};   // max X^2 without the scale
       }
     }
   }

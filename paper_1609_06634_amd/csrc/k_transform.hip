@@ -3,6 +3,7 @@
 // once per orientation or per image, Listing 1's outer loops), so it favours
 // accuracy: every step computes in FP64 and only the stored spectra are FP32.
 #include <algorithm>
+#include <cmath>
 
 #include "common.hpp"
 
@@ -713,7 +714,7 @@ __global__ __launch_bounds__(256) void k_tile_spec(const float2* __restrict__ sp
 
 // Fragment-order copy of real tables: four consecutive rows per float4.
 __global__ __launch_bounds__(256) void k_tile_table(const float* __restrict__ table, long total, int nx, int ny,
-                                                    float4* __restrict__ tile) {
+                                                    float scale, float4* __restrict__ tile) {
   const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= total) return;
   const int KS = split_ks(ny), ldy = spec_ld(ny), half = nx / 2;
@@ -726,7 +727,7 @@ __global__ __launch_bounds__(256) void k_tile_table(const float* __restrict__ ta
   float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
   if (m < half) {
     const float* c = table + (size_t)item * (nx / 2 + 1) * ldy + (size_t)m * ldy + l;
-    v = make_float4(c[0], c[1], c[2], c[3]);
+    v = make_float4(c[0] * scale, c[1] * scale, c[2] * scale, c[3] * scale);   // a power of two: exact
   }
   tile[idx] = v;
 }
@@ -738,11 +739,38 @@ hipError_t launch_tile_spec(hipStream_t s, const float2* spec, int n, int nx, in
   return last();
 }
 
-hipError_t launch_tile_table(hipStream_t s, const float* table, int n, int nx, int ny, float4* tile) {
+// The split forms take their conjugate products Z (each component at most 4
+// in magnitude with spectra scaled below 1 and CTF values at most 1) and their
+// stage-1 sums over the ny rows (at most 4 ny) as fp16 hi/lo pairs.  fp16's
+// subnormal range makes the split exact only to about 2^-24 in absolute terms,
+// which for the many small products of a large box adds up in X; the CTF
+// values are therefore scaled by 2^zs, the largest power of two that keeps the
+// stage-1 sums below 2^15 (in the tile copies and, once the projection norms
+// are taken, in the table itself), and the kernel takes 2 zs off kappa's
+// exponent.
+int split_operand_scale(int ny) {
+  int zs = 0;
+  while (4.0 * ny * std::ldexp(1.0, zs + 1) <= 32768.0) ++zs;
+  return zs;
+}
+
+__global__ __launch_bounds__(256) void k_scale_table(float* __restrict__ t, long n, float scale) {
+  const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx < n) t[idx] *= scale;
+}
+
+hipError_t launch_scale_table(hipStream_t s, float* table, size_t n, int zs) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_scale_table, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, table, (long)n,
+                     std::ldexp(1.0f, zs));
+  return last();
+}
+
+hipError_t launch_tile_table(hipStream_t s, const float* table, int n, int nx, int ny, int zs, float4* tile) {
   const long total = (long)n * (long)tile_table_len(nx, ny);
   if (total == 0) return hipSuccess;
   hipLaunchKernelGGL(k_tile_table, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, table, total, nx, ny,
-                     tile);
+                     std::ldexp(1.0f, zs), tile);
   return last();
 }
 
