@@ -149,6 +149,7 @@ const char* bioem_version(void);
  *   quats   [nq][4] float64 unit quaternions (w, x, y, z);
  *   nx, ny  even box size in pixels (4 <= n <= 512); pixel_A > 0 (kept with
  *           the handle: it also sets the CTF frequency scale in bioem_logpost).
+ * ns >= 1 and nq >= 1: an empty model or grid is BIOEM_EINVAL.
  * Each projection is I0[k][j] = sum_a w_a Ey_a[k] Ex_a[j] with pixel-box
  * integrals of the rotated Gaussians (FP64), then its half-spectrum DFT,
  * stored on the device twice: column-major, and in the matrix-fragment order
@@ -162,6 +163,8 @@ bioem_status bioem_project(bioem_ctx* ctx, const double* spheres, int32_t ns,
  * precalculated).  imgs is [ni][ny][nx] float32.  Computes, in FP64 from the
  * pixels, C_o = sum I, C_oo = sum I^2 and A = sum (I - C_o/n)^2, and the
  * half-spectrum DFT of each image (stored twice, as for bioem_project).
+ * ni >= 1 (no images is BIOEM_EINVAL); a NaN or infinite pixel is
+ * BIOEM_EINVAL before anything is enqueued.
  * *out must be released with bioem_free_imgs. */
 bioem_status bioem_prepare_images(bioem_ctx* ctx, const float* imgs, int32_t ni, int32_t nx,
                                   int32_t ny, bioem_mem in_mem, bioem_imgs** out);
@@ -169,6 +172,7 @@ bioem_status bioem_prepare_images(bioem_ctx* ctx, const float* imgs, int32_t ni,
 /* Per-image log posterior over orientations x CTF sets x shifts (Eq. Pmom,
  * Listing 1).  ctf is [nc][3] float64 (a in A^2, A in [0,1], b in A^2) of
  * CTF(s|a,A) Env(s|b) (Section 2); ctf is host or device per `ctf_mem`.
+ * nc >= 1 (no CTF sets is BIOEM_EINVAL).
  * max_shift = S with 0 <= S < min(nx, ny)/2.  Outputs: logp [ni] float64 and
  * best [ni] (either may be NULL), and optional opts->logp_orient.  opts may
  * be NULL (F32, host outputs, full grid). */

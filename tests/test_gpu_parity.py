@@ -185,6 +185,24 @@ def test_invalid_arguments(P, ctx, cfg1):
         P.logpost(ctx, proj, im2, cls.ctf, 2)             # box mismatch
 
 
+def test_empty_inputs_rejected(P, ctx, cfg1):
+    """No spheres, no orientations, no images or no CTF sets is an invalid
+    argument (EINVAL), found before any work; the handles made before stay
+    usable."""
+    wl, cls, imgs = cfg1
+    proj = P.project(ctx, wl.models[0], cls.quats[:3], cls.nx, cls.ny, cls.pixel_A)
+    im = P.prepare_images(ctx, imgs[:2])
+    cases = [lambda: P.project(ctx, wl.models[0][:0], cls.quats[:3], cls.nx, cls.ny, cls.pixel_A),
+             lambda: P.project(ctx, wl.models[0], cls.quats[:0], cls.nx, cls.ny, cls.pixel_A),
+             lambda: P.prepare_images(ctx, imgs[:0]),
+             lambda: P.logpost(ctx, proj, im, cls.ctf[:0], 2)]
+    for f in cases:
+        with pytest.raises(P.BioemError) as e:
+            f()
+        assert e.value.status == -1
+    assert np.all(np.isfinite(P.logpost(ctx, proj, im, cls.ctf, 2)["logp"]))
+
+
 def test_nonfinite_pixels_rejected(P, ctx, cfg1):
     """A NaN or infinite pixel is an invalid argument, found before any work
     (host and device images)."""
