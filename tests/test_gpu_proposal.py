@@ -88,7 +88,7 @@ def test_config5_grid_and_snr_capture_report():
     """At the proposal workload's own size and signal (36,864 orientations,
     SNR 0.1, top 256), with a short training run (5,000 labelled images, 3
     epochs): reports the fraction of held-out images the pruned posterior
-    captures (|d log P| <= 0.1 against the exhaustive judge) and the
+    captures (|d log P| <= 0.1 against the exhaustive posterior) and the
     evaluations the mass fallback saves, and checks what must hold whatever
     the network learned: the pruned value never exceeds the exhaustive one,
     and fallen-back images are exact."""
