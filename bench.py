@@ -486,7 +486,9 @@ def run_mixed(args, P, ctx, torch, dev) -> int:
             f32c / (peak * 1e12) + f64c / (PEAK_FP64_TFLOPS * 1e12))
     frac = roof_t / (p["kms"] * 1e-3)
     mixed_roof = {"bound": "mfma", "achieved": round(frac * peak, 3), "peak": peak, "unit": "TFLOP/s",
-                  "frac": round(frac, 4), "traffic": None, "kernel": "k_logpost_batch",
+                  "frac": round(frac, 4), "traffic": None,
+                  "kernel": ("k_logpost_batch" if args.prec != "f32" else
+                             "k_logpost_mf32 (one launch per job: the F32 form has no persistent launch)"),
                   "kernel_ms_per_launch": round(p["kms"] / max(p["launches"], 1), 3), "launches": p["launches"]}
     # ensemble posterior, Eq. (pb2), of the two models over every image (each
     # class holds images of both): its log posterior on a grid of weights,
@@ -521,7 +523,9 @@ def run_mixed(args, P, ctx, torch, dev) -> int:
             "data": "synthetic",
             "config": {"workload": f"mixed sizes: 96/128/180/224 px x {per} images each, two models "
                                    "(1000 and 2500 spheres), grids (1152,4) (2304,8) (3456,12) "
-                                   "(4608,16), shifts 8/11/16/20, one persistent launch",
+                                   "(4608,16), shifts 8/11/16/20, "
+                                   + ("one persistent launch" if args.prec != "f32" else
+                                      "bioem_logpost_batch (one launch per job for F32)"),
                        "evals_per_step": evals, "prec": args.prec, "autotune": not args.no_autotune,
                        "step": "bioem_project + bioem_prepare_images + bioem_logpost_batch"},
             "roofline": mixed_roof,
